@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark of the anonymized-network-sensing hot path on one MI355X.
+
+A step is one pass of the whole path over the 64-window workload: 64 windows
+of 2^17 packets (sources Zipf 1.1, destinations Zipf 1.3, pool 2^20) ->
+every window's traffic matrix and eight quantities, plus the union-added
+aggregate matrix of all windows and its eight quantities, submitted as one
+graph-captured batched call (ns_batch_stats). Inputs are resident in HBM
+before the timed region. The same work done the plain way (per-window
+ns_build_matrix + ns_stats launches and an ns_accumulate chain for the
+aggregate) is timed beside it.
+
+Prints one JSON line. `--gpus N` with N > 1 is refused: this path runs on one
+GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--workload", default="windows64",
+                   choices=["windows64", "one_window", "uneven1024", "aggregate_2p30"])
+    p.add_argument("--plain-steps", type=int, default=5)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=10.0,
+                   help="target CPU time of the oracle baseline sample")
+    return p.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this path runs on a single GPU; multi-GPU runs are not supported "
+              "(see DESIGN.md, 'Sharding')", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2510_14050_amd import ns, synth
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ns.load()
+
+    wl = synth.WORKLOADS[args.workload]()
+    W, N = wl.num_windows, wl.total_packets
+    log(f"workload {wl.name}: {W} windows, {N} packets; generating on the device")
+    src_t, dst_t = wl.device_concat(dev)
+    off_np = wl.offsets
+    off_t = torch.from_numpy(off_np).to(dev)
+    ws = ns.Workspace(N, W, device=dev)
+    out = torch.zeros((W, 8), dtype=torch.int64, device=dev)
+    agg = ns.Matrix(N, device=dev)
+    agg_stats = torch.zeros(8, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        ns.batch_stats(src_t, dst_t, off_t, out, ws, agg=agg, agg_stats=agg_stats)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = N * args.steps / (t1 - t0)
+    log(f"batched: {ms_step:.3f} ms/step, {value:.4e} packets/s")
+    got = ns.stats_numpy(out).copy()
+    got_agg = ns.stats_numpy(agg_stats).copy()
+    agg_nnz = agg.nnz()
+
+    # --- per-kernel durations from HIP events (eager replay of the same step) ---
+    ns.timing_reset()
+    ns.timing_enable(True)
+    ns.batch_stats(src_t, dst_t, off_t, out, ws, agg=agg, agg_stats=agg_stats, graph=False)
+    torch.cuda.synchronize()
+    kt = ns.timing_read()
+    ns.timing_enable(False)
+    ns.timing_reset()
+    links_windows = int(got[:, 1].sum())
+    # dominant kernel: the radix pass (key passes after the first, and column passes,
+    # which are the same kernel); algorithmic bytes = one 8-byte read + one 8-byte
+    # write per key or column item moved
+    pass_ms = kt.get("pass", (0.0, 0))[0] + kt.get("col_pass", (0.0, 0))[0]
+    pass_n = kt.get("pass", (0.0, 0))[1] + kt.get("col_pass", (0.0, 0))[1]
+    key_launches = kt.get("pass", (0.0, 0))[1]
+    items_moved = (key_launches * N) + 4 * (links_windows + agg_nnz)
+    pass_bytes = 16.0 * items_moved
+    avg_launch_ms = pass_ms / max(pass_n, 1)
+    achieved = pass_bytes / max(pass_n, 1) / (avg_launch_ms * 1e-3) / 1e9 if pass_ms else 0.0
+    breakdown = {k: {"ms": round(v[0], 4), "launches": v[1]} for k, v in kt.items()}
+    log("kernel breakdown (eager, ms):", json.dumps(breakdown))
+
+    # --- plain per-window path ---
+    plain = None
+    if not args.no_plain:
+        wins = [ns.Matrix(int(wl.sizes[w]), device=dev) for w in range(W)]
+        accs = [ns.Matrix(N, device=dev), ns.Matrix(N, device=dev)]
+        st_w = torch.zeros((W, 8), dtype=torch.int64, device=dev)
+        st_a = torch.zeros(8, dtype=torch.int64, device=dev)
+        empty = ns.Matrix(0, device=dev)
+        ns.build_matrix(src_t[:0], dst_t[:0], empty, ws)
+
+        def plain_step():
+            cur = empty
+            for w in range(W):
+                a, b = int(off_np[w]), int(off_np[w + 1])
+                ns.build_matrix(src_t[a:b], dst_t[a:b], wins[w], ws)
+                ns.stats(wins[w], st_w[w], ws)
+                nxt = accs[w & 1]
+                ns.accumulate(cur, wins[w], 1, nxt, ws)
+                cur = nxt
+            ns.stats(cur, st_a, ws)
+
+        plain_step()
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            plain_step()
+        torch.cuda.synchronize()
+        p1 = time.perf_counter()
+        plain_ms = (p1 - p0) * 1e3 / args.plain_steps
+        plain = {"value": N / (plain_ms * 1e-3), "ms_per_step": round(plain_ms, 4),
+                 "bit_exact_vs_batched": bool(np.array_equal(ns.stats_numpy(st_w), got)
+                                              and np.array_equal(ns.stats_numpy(st_a), got_agg))}
+        log(f"plain: {plain_ms:.3f} ms/step, {plain['value']:.4e} packets/s")
+
+    # --- oracle on the host: parity and CPU baseline ---
+    cpu = None
+    bit_exact = None
+    if not args.no_cpu_baseline:
+        import oracle
+        src = synth.as_u32(src_t)
+        dst = synth.as_u32(dst_t)
+        # bounded sample: whole windows (and the aggregate of the sampled windows)
+        # until about --cpu-seconds of single-threaded oracle work
+        c0 = time.perf_counter()
+        done_pk, w = 0, 0
+        want = np.zeros((W, 8), np.uint64)
+        while w < W and (time.perf_counter() - c0) < args.cpu_seconds / 2:
+            a, b = int(off_np[w]), int(off_np[w + 1])
+            want[w] = oracle.stats(src[a:b], dst[a:b])
+            done_pk += b - a
+            w += 1
+        sampled_w = w
+        sample_pk = int(off_np[sampled_w])
+        agg_want = oracle.stats(src[:sample_pk], dst[:sample_pk])
+        done_pk += sample_pk
+        c1 = time.perf_counter()
+        # the sample processes sample_pk packets per window pass and per aggregate
+        cpu_rate = sample_pk / (c1 - c0)
+        cpu = {"value": cpu_rate, "unit": "packets/s", "cores": 1, "kind": "oracle",
+               "sample": f"{sampled_w} of {W} windows ({sample_pk} packets): per-window "
+                         f"8 quantities + aggregate matrix and its 8 quantities, "
+                         f"std::sort route, single thread, {c1 - c0:.1f} s"}
+        bit_exact = bool(np.array_equal(got[:sampled_w], want[:sampled_w]))
+        if sampled_w == W:
+            bit_exact = bit_exact and bool(np.array_equal(got_agg, agg_want))
+        log(f"oracle: {cpu_rate:.4e} packets/s on {sampled_w} windows; bit-exact {bit_exact}")
+
+    line = {
+        "metric": "packets/sec (8 stats, bit-exact) batched vs plain; p50/p99 window latency",
+        "value": value,
+        "unit": "packets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "windows": W, "total_packets": N,
+                   "outputs": "per-window 8 stats + aggregate matrix + aggregate 8 stats",
+                   "submission": "one HIP graph (ns_batch_stats)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": None,
+                     "kernel": "ns::k_pass<256,16,false> (radix pass, key and column)",
+                     "avg_launch_ms": round(avg_launch_ms, 5), "launches": pass_n,
+                     "algorithmic_bytes_per_launch": round(pass_bytes / max(pass_n, 1))},
+        "cpu_baseline": cpu,
+        "plain": plain,
+        "batched_vs_plain": round(value / plain["value"], 2) if plain else None,
+        "bit_exact": bit_exact,
+        "kernels_ms": breakdown,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * ns.h -- C ABI of libns.so: anonymized network sensing on MI355X (gfx950).
+ *
+ * A window is a multiset of packets, each a (source, destination) pair of
+ * 32-bit anonymized IPv4 addresses. Its traffic matrix A has A(i,j) = number
+ * of packets from source i to destination j (Table I caption). The library
+ * builds A as a hypersparse 2^32 x 2^32 matrix in sorted COO form and reduces
+ * it to the eight quantities of ns_stats_t.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers are DEVICE pointers unless marked "host". Buffers are owned by
+ *     the caller (the library never allocates device memory); the library only
+ *     reads inputs and writes outputs and the caller's workspace.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the default
+ *     stream). Results are valid once the stream reaches the call.
+ *   - Return 0 (NS_OK) or a negative NS_ERR_* code. Argument and capacity
+ *     errors are found on the host before anything is enqueued; then outputs
+ *     are untouched. No device-to-host synchronisation happens on any hot path:
+ *     capacities are checked against host-known bounds (packet counts), and
+ *     sizes produced on the device (nnz) stay on the device.
+ *   - Packet counts per window / per matrix must be below 2^32.
+ *   - `ws` is caller workspace of at least ns_workspace_size() bytes, 256-byte
+ *     aligned. Calls that share one workspace must be ordered on one stream.
+ */
+#ifndef NS_H_
+#define NS_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  NS_OK = 0,
+  NS_ERR_INVALID_ARG = -1,  /* null pointer, bad size, aliasing, bad sign */
+  NS_ERR_CAPACITY = -2,     /* an output's capacity is below the a-priori bound */
+  NS_ERR_WORKSPACE = -3,    /* ws too small or misaligned */
+  NS_ERR_HIP = -4,          /* a HIP runtime call failed */
+  NS_ERR_UNDERFLOW = -5,    /* subtraction below zero (host-detected, or via ns_device_status) */
+  NS_ERR_UNSUPPORTED = -6   /* size beyond the supported range (>= 2^32 packets) */
+};
+
+/* The eight quantities, all exact uint64, in this fixed order (64 bytes).
+ *   valid_packets        sum_i sum_j A(i,j)                         Table I
+ *   unique_links         number of (i,j) with A(i,j) > 0            Table I
+ *   unique_sources       number of rows i with sum_j A(i,j) > 0     Table I
+ *   unique_destinations  number of columns j with sum_i A(i,j) > 0  Table I
+ *   max_source_packets   max_i sum_j A(i,j)        (row sums, Sec. IV data representation)
+ *   max_source_fanout    max_i #{j : A(i,j) > 0}   (Table I, read as the row's nonzero count)
+ *   max_destination_packets  max_j sum_i A(i,j)    (column sums, Sec. IV)
+ *   max_destination_fanin    max_j #{i : A(i,j) > 0} (Table I, column nonzero count)
+ * An empty window has all eight equal to 0. */
+typedef struct {
+  uint64_t valid_packets;
+  uint64_t unique_links;
+  uint64_t unique_sources;
+  uint64_t unique_destinations;
+  uint64_t max_source_packets;
+  uint64_t max_source_fanout;
+  uint64_t max_destination_packets;
+  uint64_t max_destination_fanin;
+} ns_stats_t;
+
+/* A traffic matrix in sorted COO form: a NON-OWNING view of caller buffers.
+ *   keys[k]   = (uint64)source << 32 | destination, strictly increasing on [0, *nnz)
+ *   counts[k] = A(source, destination) >= 1
+ *   nnz       device scalar, written by the library
+ *   capacity  host: entries allocated in keys and in counts
+ *   packets   host: exact number of packets the matrix represents (= sum of
+ *             counts); set by the library on every output matrix. */
+typedef struct {
+  uint64_t *keys;
+  uint64_t *counts;
+  uint64_t *nnz;
+  uint64_t capacity;
+  uint64_t packets;
+} ns_matrix_t;
+
+/* Launch shape of the batched path. 0 in any field selects the built-in
+ * default; the autotuner in the Python package fills these from its cache.
+ *   sort_block   workgroup size of the radix passes (256 or 512)
+ *   sort_items   keys per thread in a radix pass (8 or 16): tile = block*items
+ *   digit_bits   radix digit width (8)
+ *   scan_items   positions per thread in the run-length / run-reduce passes (4 or 8) */
+typedef struct {
+  uint32_t sort_block;
+  uint32_t sort_items;
+  uint32_t digit_bits;
+  uint32_t scan_items;
+} ns_tuning_t;
+
+/* Per-window matrices of a batch, stored back to back (batched COO).
+ * Window w owns entries [offsets[w], offsets[w+1]) of keys/counts; offsets
+ * has num_windows+1 device entries written by the library; capacity (host)
+ * must be >= the batch's total packets. */
+typedef struct {
+  uint64_t *keys;
+  uint64_t *counts;
+  uint64_t *offsets;
+  uint64_t capacity;
+} ns_batch_matrices_t;
+
+/* Bytes of workspace sufficient for every entry point called with at most
+ * `max_packets` packets (or matrix entries / capacity) in total and at most
+ * `num_windows` windows. Host-only; writes *bytes (host). */
+int ns_workspace_size(uint64_t max_packets, uint32_t num_windows, uint64_t *bytes);
+
+/* Build the traffic matrix of one window (Table I caption: A(i,j) counts the
+ * packets from i to j). src/dst: n uint32 each. out->keys and out->counts must
+ * hold at least n entries (they double as the sort's ping-pong buffers);
+ * out->packets is set to n; *out->nnz is written on the device. n = 0 gives an
+ * empty matrix. */
+int ns_build_matrix(const uint32_t *src, const uint32_t *dst, uint64_t n, ns_matrix_t *out,
+                    void *ws, uint64_t ws_bytes, void *stream);
+
+/* Union-add (sign = +1) or subtract (sign = -1) of two matrices: acc_out(i,j)
+ * = acc_in(i,j) + sign*win(i,j), structure = union, entries that reach zero
+ * are dropped ("load and aggregate", Fig. 2 caption; subtraction is its exact
+ * inverse and serves rolling windows). acc_out must not alias either input.
+ * Capacity: acc_out->capacity >= min(acc_in cap, acc_in packets) + min(win
+ * cap, win packets) for add, >= min(acc_in cap, acc_in packets) for subtract.
+ * Subtracting more packets than acc_in holds is rejected on the host; an
+ * entry of win that is absent from or larger than acc_in is detected on the
+ * device and reported by ns_device_status (acc_out is then undefined). */
+int ns_accumulate(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
+                  ns_matrix_t *acc_out, void *ws, uint64_t ws_bytes, void *stream);
+
+/* The eight quantities of a matrix (Table I with the row/column-sum maxima)
+ * into *out (device). m->packets must be below 2^32. */
+int ns_stats(const ns_matrix_t *m, ns_stats_t *out, void *ws, uint64_t ws_bytes, void *stream);
+
+/* Batched path: the eight quantities of each of num_windows windows in one
+ * submission (captured once as a HIP graph and replayed; sizes are read from
+ * device memory, so the graph holds for any window sizes within the bounds).
+ *   src, dst      concatenated packets of all windows (total_packets each)
+ *   offsets       device [num_windows+1], offsets[0] = 0, non-decreasing,
+ *                 offsets[num_windows] = total_packets; window w = [offsets[w], offsets[w+1])
+ *   total_packets host bound, equal to offsets[num_windows]
+ *   out           device [num_windows] results
+ *   agg_out       nullable: union-add of all windows (capacity >= total_packets)
+ *   agg_stats     nullable: device ns_stats_t of agg_out (requires agg_out)
+ *   win_out       nullable: every window's own matrix (batched COO)
+ *   tune          nullable: launch shape (NULL = defaults)
+ * Windows may be empty. Each window must hold fewer than 2^32 packets. */
+int ns_batch_stats(const uint32_t *src, const uint32_t *dst, const uint64_t *offsets,
+                   uint32_t num_windows, uint64_t total_packets, ns_stats_t *out,
+                   ns_matrix_t *agg_out, ns_stats_t *agg_stats, ns_batch_matrices_t *win_out,
+                   const ns_tuning_t *tune, void *ws, uint64_t ws_bytes, void *stream);
+
+/* Same computation as ns_batch_stats, enqueued kernel by kernel without a
+ * graph (used to compare graph and eager submission). */
+int ns_batch_stats_eager(const uint32_t *src, const uint32_t *dst, const uint64_t *offsets,
+                         uint32_t num_windows, uint64_t total_packets, ns_stats_t *out,
+                         ns_matrix_t *agg_out, ns_stats_t *agg_stats,
+                         ns_batch_matrices_t *win_out, const ns_tuning_t *tune, void *ws,
+                         uint64_t ws_bytes, void *stream);
+
+/* Synchronises `stream`, then reads and clears the current device's error
+ * word: *status (host) = NS_OK or NS_ERR_UNDERFLOW. */
+int ns_device_status(void *stream, int *status);
+
+/* Destroys every cached HIP graph (call before freeing buffers a cached graph
+ * refers to, or to bound memory). */
+int ns_release_graphs(void);
+
+/* Kernel timing for measurement (not on any hot path). While enabled, the
+ * eager entry points (all but ns_batch_stats, whose graph is left untouched)
+ * record a pair of HIP events on the launching stream around every kernel
+ * launch. ns_timing_read synchronises those events and returns, for one
+ * kernel kind, the summed duration (host *total_ms) and the number of
+ * launches (host *launches). Kinds: 0 fill, 1 tile setup, 2 digit histogram,
+ * 3 histogram scan, 4 first radix pass (packs keys), 5 other key radix passes,
+ * 6 column radix passes, 7 run-length encoding, 8 run reduction,
+ * 9 segment maxima, 10 finalize, 11 merge. ns_timing_reset destroys the
+ * recorded events. */
+int ns_timing_enable(int on);
+int ns_timing_reset(void);
+int ns_timing_read(uint32_t kind, double *total_ms, uint64_t *launches);
+
+/* Static description of an error code. */
+const char *ns_error_string(int code);
+
+/* Library version string. */
+const char *ns_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NS_H_ */

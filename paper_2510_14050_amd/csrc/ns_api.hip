@@ -1,0 +1,704 @@
+// C ABI of libns (declared in include/ns.h): argument checks, workspace
+// layout, the kernel sequence of each entry point, and the HIP-graph cache of
+// the batched path.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/ns.h"
+#include "ns_launch.h"
+
+using namespace ns;
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+constexpr int kMaxTickets = 64;
+constexpr uint64_t kMaxPackets32 = 0xFFFFFFFFull;  // packets per window / matrix < 2^32
+constexpr int kMinSortTile = 256 * 8;
+constexpr int kMinScanTile = 256 * 4;
+
+uint64_t up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// Workspace carve-up for at most N packets / entries and W windows.
+struct Layout {
+  uint64_t tickets, seg, t_sort, t_hist, t_rle, t_csort, t_run;
+  uint64_t link_off, row_off, col_off;
+  uint64_t hist, base, chist, cbase;
+  uint64_t lb0, lb1, lbs;
+  uint64_t KA, KB, HA, HB;
+  uint64_t total;
+  uint64_t sort_tiles, scan_tiles;
+};
+
+Layout plan(uint64_t N, uint32_t W) {
+  Layout L{};
+  const uint64_t W1 = (uint64_t)W + 1 > 2 ? (uint64_t)W + 1 : 2;
+  const uint64_t Wd = W > 1 ? W : 1;
+  L.sort_tiles = N / kMinSortTile + Wd + 1;
+  L.scan_tiles = N / kMinScanTile + Wd + 1;
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) { const uint64_t at = o; o += up(bytes); return at; };
+  L.tickets = take(kMaxTickets * 4);
+  L.seg = take(W1 * 8);
+  L.t_sort = take(W1 * 8);
+  L.t_hist = take(W1 * 8);
+  L.t_rle = take(W1 * 8);
+  L.t_csort = take(W1 * 8);
+  L.t_run = take(W1 * 8);
+  L.link_off = take(W1 * 8);
+  L.row_off = take(W1 * 8);
+  L.col_off = take(W1 * 8);
+  L.hist = take(Wd * kKeyDigits * kBins * 4);
+  L.base = take(Wd * kKeyDigits * kBins * 4);
+  L.chist = take(Wd * kColDigits * kBins * 4);
+  L.cbase = take(Wd * kColDigits * kBins * 4);
+  L.lb0 = take(L.sort_tiles * kBins * 8);
+  L.lb1 = take(L.sort_tiles * kBins * 8);
+  L.lbs = take(L.scan_tiles * 2 * 8);
+  L.KA = take((N + 1) * 8);
+  L.KB = take((N + 1) * 8);
+  L.HA = take((N + 2) * 8);
+  L.HB = take((N + 2) * 8);
+  L.total = o;
+  return L;
+}
+
+// Pointers into a caller workspace.
+struct Ws {
+  Layout L;
+  uint8_t *base;
+  int next_ticket = 0;
+  template <typename T>
+  T *at(uint64_t off) const { return reinterpret_cast<T *>(base + off); }
+  uint32_t *ticket() { return at<uint32_t>(L.tickets) + (next_ticket++ % kMaxTickets); }
+};
+
+#define HIP_TRY(expr)                           \
+  do {                                          \
+    if ((expr) != hipSuccess) return NS_ERR_HIP; \
+  } while (0)
+
+// Optional per-kernel timing: HIP events recorded on the launching stream
+// around every launch of the eager paths (never inside a captured graph).
+enum Kind { K_FILL, K_TILES, K_HIST, K_HSCAN, K_PASS0, K_PASS, K_CPASS, K_RLE, K_RUNS, K_SEGMAX,
+            K_FINAL, K_MERGE, K_COUNT };
+
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  struct Mark { int kind; hipEvent_t a, b; };
+  std::vector<Mark> marks;
+};
+
+Profiler &prof() {
+  static Profiler *p = new Profiler();
+  return *p;
+}
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st != hipStreamCaptureStatusNone;
+}
+
+// Runs `launch` (returning hipError_t), bracketed by events when timing is on.
+template <typename F>
+hipError_t timed(int kind, hipStream_t s, F launch) {
+  Profiler &p = prof();
+  if (!p.on || capturing(s)) return launch();
+  Profiler::Mark m{kind, nullptr, nullptr};
+  if (hipEventCreate(&m.a) != hipSuccess || hipEventCreate(&m.b) != hipSuccess) return launch();
+  hipError_t e = hipEventRecord(m.a, s);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(m.b, s);
+  std::lock_guard<std::mutex> lock(p.mu);
+  p.marks.push_back(m);
+  return e;
+}
+
+int check_ws(void *ws, uint64_t ws_bytes, uint64_t N, uint32_t W, Ws *out) {
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return NS_ERR_WORKSPACE;
+  out->L = plan(N, W);
+  if (ws_bytes < out->L.total) return NS_ERR_WORKSPACE;
+  out->base = static_cast<uint8_t *>(ws);
+  return NS_OK;
+}
+
+struct Shapes {
+  SortShape sort;
+  ScanShape scan;
+};
+
+int resolve_tuning(const ns_tuning_t *t, Shapes *sh) {
+  sh->sort = {256, 16};
+  sh->scan = {8};
+  if (!t) return NS_OK;
+  if (t->digit_bits && t->digit_bits != 8) return NS_ERR_INVALID_ARG;
+  if (t->sort_block) {
+    if (t->sort_block != 256 && t->sort_block != 512) return NS_ERR_INVALID_ARG;
+    sh->sort.block = (int)t->sort_block;
+  }
+  if (t->sort_items) {
+    if (t->sort_items != 8 && t->sort_items != 16) return NS_ERR_INVALID_ARG;
+    sh->sort.items = (int)t->sort_items;
+  }
+  if (t->scan_items) {
+    if (t->scan_items != 4 && t->scan_items != 8) return NS_ERR_INVALID_ARG;
+    sh->scan.items = (int)t->scan_items;
+  }
+  return NS_OK;
+}
+
+// Column pass shared by every statistics path: items dst<<32|count of each
+// link segment (segments [link_off[w], link_off[w+1]) in items_in) are
+// radix-sorted by destination, then destination runs give unique
+// destinations, max fan-in and max destination packets.
+// On return the sorted items are in `tmp` (4 passes: in -> tmp -> in -> tmp -> in
+// ... ends in items_in).
+int enqueue_columns(Ws &ws, const Shapes &sh, uint64_t *items, uint64_t *tmp,
+                    const uint64_t *link_off, uint32_t W, uint64_t max_items,
+                    const uint32_t *chist, uint64_t *stats, hipStream_t s) {
+  const Layout &L = ws.L;
+  uint64_t *t_csort = ws.at<uint64_t>(L.t_csort), *t_run = ws.at<uint64_t>(L.t_run);
+  uint32_t *cbase = ws.at<uint32_t>(L.cbase);
+  HIP_TRY(timed(K_TILES, s, [&] { return launch_tiles(link_off, W, sh.sort.tile(), t_csort, sh.scan.tile(), t_run, 1, nullptr, s); }));
+  HIP_TRY(timed(K_HSCAN, s, [&] { return launch_hist_scan(chist, cbase, (uint64_t)W * kColDigits, s); }));
+  const uint64_t sort_tiles = max_items / sh.sort.tile() + W + 1;
+  uint64_t *lb[2] = {ws.at<uint64_t>(L.lb0), ws.at<uint64_t>(L.lb1)};
+  uint64_t *buf[2] = {items, tmp};
+  for (int q = 0; q < kColDigits; ++q) {
+    PassArgs a{};
+    a.in = buf[q & 1];
+    a.out = buf[(q + 1) & 1];
+    a.seg_off = link_off;
+    a.tile_off = t_csort;
+    a.W = W;
+    a.shift = 32 + 8 * q;
+    a.base = cbase + q * kBins;
+    a.base_stride = kColDigits * kBins;
+    a.lb = lb[q & 1];
+    a.lb_next = lb[(q + 1) & 1];
+    a.ticket = ws.ticket();
+    HIP_TRY(timed(K_CPASS, s, [&] { return launch_pass(sh.sort, a, sort_tiles, s); }));
+  }
+  // 4 passes: sorted items are back in `items`
+  uint64_t *lbs = ws.at<uint64_t>(L.lbs);
+  uint64_t *hpos = ws.at<uint64_t>(L.HA), *hval = ws.at<uint64_t>(L.HB);
+  uint64_t *col_off = ws.at<uint64_t>(L.col_off);
+  const uint64_t run_tiles = max_items / sh.scan.tile() + W + 1;
+  HIP_TRY(launch_fill64(lbs, run_tiles * 2, 0, s));
+  HIP_TRY(launch_fill64(col_off, (uint64_t)W + 1, 0, s));
+  HIP_TRY(launch_fill64(hpos, 1, 0, s));
+  HIP_TRY(launch_fill64(hval, 1, 0, s));
+  RunArgs r{};
+  r.keys = items;
+  r.seg_off = link_off;
+  r.tile_off = t_run;
+  r.W = W;
+  r.hpos = hpos;
+  r.hval = hval;
+  r.head_off = col_off;
+  r.lb = lbs;
+  r.ticket = ws.ticket();
+  HIP_TRY(timed(K_RUNS, s, [&] { return launch_runs(sh.scan, 1, r, run_tiles, s); }));
+  // fan-in = run length, destination packets = run sum
+  HIP_TRY(timed(K_SEGMAX, s, [&] { return launch_segmax(hpos, hval, col_off, W, max_items, stats, 7, 6, s); }));
+  return NS_OK;
+}
+
+// Full pipeline from packets: radix sort of the packed keys of W segments,
+// run-length encoding, and (optionally) the eight quantities per segment.
+struct PacketOut {
+  uint64_t *stats;         // [W][8] or null
+  uint64_t *ukeys;         // matrix keys (may be the in-place sorted buffer) or null
+  uint64_t *counts;        // matrix counts or null
+  uint64_t *nnz;           // total links (device scalar) or null
+  uint64_t *link_off;      // [W+1] output offsets (or null: workspace)
+  uint64_t *sort_a;        // sort ping-pong buffers (capacity >= N each); the sorted
+  uint64_t *sort_b;        // keys end in sort_b
+};
+
+int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_t *dst,
+                    const uint64_t *seg_off, uint32_t W, uint64_t N, const PacketOut &o,
+                    hipStream_t s) {
+  const Layout &L = ws.L;
+  uint64_t *t_sort = ws.at<uint64_t>(L.t_sort), *t_hist = ws.at<uint64_t>(L.t_hist),
+           *t_rle = ws.at<uint64_t>(L.t_rle);
+  uint32_t *hist = ws.at<uint32_t>(L.hist), *base = ws.at<uint32_t>(L.base);
+  uint32_t *chist = ws.at<uint32_t>(L.chist);
+  uint64_t *link_off = o.link_off ? o.link_off : ws.at<uint64_t>(L.link_off);
+  uint64_t *row_off = ws.at<uint64_t>(L.row_off);
+  uint64_t *lb[2] = {ws.at<uint64_t>(L.lb0), ws.at<uint64_t>(L.lb1)};
+  const uint64_t sort_tiles = N / sh.sort.tile() + W + 1;
+  const uint64_t rle_tiles = N / sh.scan.tile() + W + 1;
+  const uint64_t hist_tiles = N / kHistTile + W + 1;
+  const bool want_stats = o.stats != nullptr;
+
+  HIP_TRY(launch_fill32(hist, (uint64_t)W * kKeyDigits * kBins, 0, s));
+  if (want_stats) {
+    HIP_TRY(launch_fill32(chist, (uint64_t)W * kColDigits * kBins, 0, s));
+    HIP_TRY(launch_fill64(o.stats, (uint64_t)W * 8, 0, s));
+  }
+  HIP_TRY(launch_fill64(lb[0], sort_tiles * kBins, 0, s));
+  HIP_TRY(launch_fill64(link_off, (uint64_t)W + 1, 0, s));
+  HIP_TRY(launch_fill64(row_off, (uint64_t)W + 1, 0, s));
+  if (o.nnz) HIP_TRY(launch_fill64(o.nnz, 1, 0, s));
+  HIP_TRY(launch_tiles(seg_off, W, sh.sort.tile(), t_sort, kHistTile, t_hist, sh.scan.tile(),
+                       t_rle, s));
+  HIP_TRY(timed(K_HIST, s, [&] { return launch_hist_packets(src, dst, seg_off, t_hist, W, hist_tiles, hist, s); }));
+  HIP_TRY(timed(K_HSCAN, s, [&] { return launch_hist_scan(hist, base, (uint64_t)W * kKeyDigits, s); }));
+  // 8 stable byte passes, least significant first; pass p writes buf[p & 1]
+  uint64_t *buf[2] = {o.sort_a, o.sort_b};
+  for (int p = 0; p < kKeyDigits; ++p) {
+    PassArgs a{};
+    if (p == 0) {
+      a.src = src;
+      a.dst = dst;
+    } else {
+      a.in = buf[(p - 1) & 1];
+    }
+    a.out = buf[p & 1];
+    a.seg_off = seg_off;
+    a.tile_off = t_sort;
+    a.W = W;
+    a.shift = 8 * p;
+    a.base = base + p * kBins;
+    a.base_stride = kKeyDigits * kBins;
+    a.lb = lb[p & 1];
+    a.lb_next = lb[(p + 1) & 1];
+    a.ticket = ws.ticket();
+    HIP_TRY(timed(p == 0 ? K_PASS0 : K_PASS, s,
+                  [&] { return launch_pass(sh.sort, a, sort_tiles, s); }));
+  }
+  uint64_t *sorted = buf[(kKeyDigits - 1) & 1];  // == sort_b
+  // run-length encoding (+ rows and column items when statistics are wanted)
+  uint64_t *lbs = ws.at<uint64_t>(L.lbs);
+  HIP_TRY(launch_fill64(lbs, rle_tiles * 2, 0, s));
+  uint64_t *items = nullptr, *rpos = nullptr, *rlink = nullptr;
+  if (want_stats) {
+    items = ws.at<uint64_t>(L.KA) == sorted ? ws.at<uint64_t>(L.KB) : ws.at<uint64_t>(L.KA);
+    rpos = ws.at<uint64_t>(L.HA);
+    rlink = ws.at<uint64_t>(L.HB);
+    HIP_TRY(launch_fill64(rpos, 1, 0, s));
+    HIP_TRY(launch_fill64(rlink, 1, 0, s));
+  }
+  RleArgs r{};
+  r.keys = sorted;
+  r.seg_off = seg_off;
+  r.tile_off = t_rle;
+  r.W = W;
+  r.ukeys = o.ukeys;
+  r.counts = o.counts;
+  r.items = items;
+  r.rpos = rpos;
+  r.rlink = rlink;
+  r.col_hist = want_stats ? chist : nullptr;
+  r.link_off = link_off;
+  r.row_off = row_off;
+  r.nnz_out = o.nnz;
+  r.lb = lbs;
+  r.ticket = ws.ticket();
+  HIP_TRY(timed(K_RLE, s, [&] { return launch_rle(sh.scan, r, rle_tiles, s); }));
+  if (!want_stats) return NS_OK;
+  // rows: packets = distance between row heads, fan-out = links between them
+  HIP_TRY(timed(K_SEGMAX, s, [&] { return launch_segmax(rpos, rlink, row_off, W, N, o.stats, 4, 5, s); }));
+  // columns: items are sorted in place (ping-pong with the other sort buffer)
+  uint64_t *tmp = (items == ws.at<uint64_t>(L.KA)) ? ws.at<uint64_t>(L.KB) : ws.at<uint64_t>(L.KA);
+  int rc = enqueue_columns(ws, sh, items, tmp, link_off, W, N, chist, o.stats, s);
+  if (rc) return rc;
+  HIP_TRY(timed(K_FINAL, s, [&] { return launch_finalize(seg_off, link_off, row_off, ws.at<uint64_t>(L.col_off), W, o.stats, s); }));
+  return NS_OK;
+}
+
+// The eight quantities of a sorted COO matrix.
+int enqueue_matrix_stats(Ws &ws, const Shapes &sh, const ns_matrix_t *m, uint64_t *stats,
+                         hipStream_t s) {
+  const Layout &L = ws.L;
+  const uint64_t cap = m->capacity < m->packets ? m->capacity : m->packets;
+  uint64_t *seg = ws.at<uint64_t>(L.seg);
+  uint64_t *t_run = ws.at<uint64_t>(L.t_run);
+  uint64_t *link_off = ws.at<uint64_t>(L.link_off);
+  uint64_t *row_off = ws.at<uint64_t>(L.row_off);
+  uint32_t *chist = ws.at<uint32_t>(L.chist);
+  uint64_t *items = ws.at<uint64_t>(L.KA), *tmp = ws.at<uint64_t>(L.KB);
+  uint64_t *hpos = ws.at<uint64_t>(L.HA), *hval = ws.at<uint64_t>(L.HB);
+  uint64_t *lbs = ws.at<uint64_t>(L.lbs);
+  const uint64_t run_tiles = cap / sh.scan.tile() + 2;
+
+  HIP_TRY(launch_fill64(stats, 8, 0, s));
+  HIP_TRY(launch_fill32(chist, kColDigits * kBins, 0, s));
+  HIP_TRY(launch_fill64(ws.at<uint64_t>(L.lb0), (cap / sh.sort.tile() + 2) * kBins, 0, s));
+  HIP_TRY(launch_fill64(lbs, run_tiles * 2, 0, s));
+  HIP_TRY(launch_fill64(row_off, 2, 0, s));
+  HIP_TRY(launch_fill64(hpos, 1, 0, s));
+  HIP_TRY(launch_fill64(hval, 1, 0, s));
+  HIP_TRY(launch_seg1(seg, m->nnz, cap, s));
+  HIP_TRY(launch_seg1(link_off, m->nnz, cap, s));
+  HIP_TRY(timed(K_TILES, s, [&] { return launch_tiles(seg, 1, sh.scan.tile(), t_run, 1, nullptr, 1, nullptr, s); }));
+  RunArgs r{};
+  r.keys = m->keys;
+  r.counts = m->counts;
+  r.seg_off = seg;
+  r.tile_off = t_run;
+  r.W = 1;
+  r.hpos = hpos;
+  r.hval = hval;
+  r.head_off = row_off;
+  r.items = items;
+  r.col_hist = chist;
+  r.lb = lbs;
+  r.ticket = ws.ticket();
+  HIP_TRY(timed(K_RUNS, s, [&] { return launch_runs(sh.scan, 0, r, run_tiles, s); }));
+  // fan-out = run length, source packets = run sum
+  HIP_TRY(timed(K_SEGMAX, s, [&] { return launch_segmax(hpos, hval, row_off, 1, cap, stats, 5, 4, s); }));
+  // valid packets = value sentinel, read before the column pass reuses hpos/hval
+  HIP_TRY(timed(K_FINAL, s, [&] { return launch_finalize_matrix(hval, row_off, nullptr, m->nnz, stats, s); }));
+  int rc = enqueue_columns(ws, sh, items, tmp, link_off, 1, cap, chist, stats, s);
+  if (rc) return rc;
+  HIP_TRY(timed(K_FINAL, s, [&] { return launch_finalize_matrix(nullptr, nullptr, ws.at<uint64_t>(L.col_off), nullptr, stats, s); }));
+  return NS_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// graph cache for the batched path
+// ===========================================================================
+namespace {
+
+struct GraphCache {
+  std::mutex mu;
+  std::unordered_map<std::string, hipGraphExec_t> execs;
+  hipStream_t capture[64] = {};
+};
+
+GraphCache &cache() {
+  static GraphCache *c = new GraphCache();  // never destroyed: graphs may outlive statics
+  return *c;
+}
+
+struct BatchArgs {
+  const uint32_t *src, *dst;
+  const uint64_t *offsets;
+  uint32_t W;
+  uint64_t N;
+  ns_stats_t *out;
+  ns_matrix_t *agg;
+  ns_stats_t *agg_stats;
+  ns_batch_matrices_t *win;
+  Shapes sh;
+};
+
+int enqueue_batch(const BatchArgs &b, Ws &ws, hipStream_t s) {
+  HIP_TRY(launch_fill32(ws.at<uint32_t>(ws.L.tickets), kMaxTickets, 0, s));
+  if (b.W > 0) {
+    PacketOut o{};
+    o.stats = reinterpret_cast<uint64_t *>(b.out);
+    o.sort_a = ws.at<uint64_t>(ws.L.KA);
+    o.sort_b = ws.at<uint64_t>(ws.L.KB);
+    if (b.win) {
+      o.ukeys = b.win->keys;
+      o.counts = b.win->counts;
+      o.link_off = b.win->offsets;
+    }
+    int rc = enqueue_packets(ws, b.sh, b.src, b.dst, b.offsets, b.W, b.N, o, s);
+    if (rc) return rc;
+  }
+  if (b.agg) {
+    uint64_t *seg = ws.at<uint64_t>(ws.L.seg);
+    HIP_TRY(launch_seg1(seg, nullptr, b.N, s));
+    PacketOut o{};
+    o.stats = reinterpret_cast<uint64_t *>(b.agg_stats);
+    o.ukeys = b.agg->keys;
+    o.counts = b.agg->counts;
+    o.nnz = b.agg->nnz;
+    o.sort_a = b.agg->counts;
+    o.sort_b = b.agg->keys;
+    int rc = enqueue_packets(ws, b.sh, b.src, b.dst, seg, 1, b.N, o, s);
+    if (rc) return rc;
+  }
+  return NS_OK;
+}
+
+int batch_checks(const uint32_t *src, const uint32_t *dst, const uint64_t *offsets, uint32_t W,
+                 uint64_t N, ns_stats_t *out, ns_matrix_t *agg, ns_stats_t *agg_stats,
+                 ns_batch_matrices_t *win, const ns_tuning_t *tune, void *ws, uint64_t ws_bytes,
+                 BatchArgs *b, Ws *w) {
+  if (N > 0 && (!src || !dst)) return NS_ERR_INVALID_ARG;
+  if (W > 0 && (!offsets || !out)) return NS_ERR_INVALID_ARG;
+  if (W == 0 && N > 0) return NS_ERR_INVALID_ARG;
+  if (N > kMaxPackets32) return NS_ERR_UNSUPPORTED;
+  if (agg_stats && !agg) return NS_ERR_INVALID_ARG;
+  if (agg) {
+    if (!agg->keys || !agg->counts || !agg->nnz) return NS_ERR_INVALID_ARG;
+    if (agg->capacity < N) return NS_ERR_CAPACITY;
+  }
+  if (win) {
+    if (!win->keys || !win->counts || !win->offsets) return NS_ERR_INVALID_ARG;
+    if (win->capacity < N) return NS_ERR_CAPACITY;
+  }
+  b->sh = Shapes{};
+  int rc = resolve_tuning(tune, &b->sh);
+  if (rc) return rc;
+  rc = check_ws(ws, ws_bytes, N, W, w);
+  if (rc) return rc;
+  b->src = src;
+  b->dst = dst;
+  b->offsets = offsets;
+  b->W = W;
+  b->N = N;
+  b->out = out;
+  b->agg = agg;
+  b->agg_stats = agg_stats;
+  b->win = win;
+  return NS_OK;
+}
+
+std::string batch_key(int dev, const BatchArgs &b, void *ws, uint64_t ws_bytes) {
+  char buf[512];
+  snprintf(buf, sizeof buf, "%d|%p|%p|%p|%u|%llu|%p|%p|%p|%p|%llu|%p|%p|%p|%p|%p|%llu|%d,%d,%d|%p|%llu",
+           dev, (const void *)b.src, (const void *)b.dst, (const void *)b.offsets, b.W,
+           (unsigned long long)b.N, (void *)b.out, b.agg ? (void *)b.agg->keys : nullptr,
+           b.agg ? (void *)b.agg->counts : nullptr, b.agg ? (void *)b.agg->nnz : nullptr,
+           (unsigned long long)(b.agg ? b.agg->capacity : 0), (void *)b.agg_stats,
+           b.win ? (void *)b.win->keys : nullptr, b.win ? (void *)b.win->counts : nullptr,
+           b.win ? (void *)b.win->offsets : nullptr, (void *)nullptr,
+           (unsigned long long)(b.win ? b.win->capacity : 0), b.sh.sort.block, b.sh.sort.items,
+           b.sh.scan.items, ws, (unsigned long long)ws_bytes);
+  return std::string(buf);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *ns_version(void) { return "libns 1.0 (gfx950)"; }
+
+const char *ns_error_string(int code) {
+  switch (code) {
+    case NS_OK: return "ok";
+    case NS_ERR_INVALID_ARG: return "invalid argument";
+    case NS_ERR_CAPACITY: return "output capacity below the a-priori bound";
+    case NS_ERR_WORKSPACE: return "workspace too small or not 256-byte aligned";
+    case NS_ERR_HIP: return "HIP runtime error";
+    case NS_ERR_UNDERFLOW: return "subtraction below zero";
+    case NS_ERR_UNSUPPORTED: return "size beyond the supported range";
+    default: return "unknown error";
+  }
+}
+
+int ns_workspace_size(uint64_t max_packets, uint32_t num_windows, uint64_t *bytes) {
+  if (!bytes) return NS_ERR_INVALID_ARG;
+  *bytes = plan(max_packets, num_windows).total;
+  return NS_OK;
+}
+
+int ns_build_matrix(const uint32_t *src, const uint32_t *dst, uint64_t n, ns_matrix_t *out,
+                    void *ws, uint64_t ws_bytes, void *stream) {
+  if (!out || !out->keys || !out->counts || !out->nnz) return NS_ERR_INVALID_ARG;
+  if (n > 0 && (!src || !dst)) return NS_ERR_INVALID_ARG;
+  if (n > kMaxPackets32) return NS_ERR_UNSUPPORTED;
+  if (out->capacity < n) return NS_ERR_CAPACITY;
+  Ws w;
+  int rc = check_ws(ws, ws_bytes, n, 1, &w);
+  if (rc) return rc;
+  Shapes sh;
+  resolve_tuning(nullptr, &sh);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(launch_fill32(w.at<uint32_t>(w.L.tickets), kMaxTickets, 0, s));
+  uint64_t *seg = w.at<uint64_t>(w.L.seg);
+  HIP_TRY(launch_seg1(seg, nullptr, n, s));
+  PacketOut o{};
+  o.ukeys = out->keys;
+  o.counts = out->counts;
+  o.nnz = out->nnz;
+  o.sort_a = out->counts;
+  o.sort_b = out->keys;
+  rc = enqueue_packets(w, sh, src, dst, seg, 1, n, o, s);
+  if (rc) return rc;
+  out->packets = n;
+  return NS_OK;
+}
+
+int ns_stats(const ns_matrix_t *m, ns_stats_t *out, void *ws, uint64_t ws_bytes, void *stream) {
+  if (!m || !out || !m->keys || !m->counts || !m->nnz) return NS_ERR_INVALID_ARG;
+  if (m->packets > kMaxPackets32) return NS_ERR_UNSUPPORTED;
+  const uint64_t cap = m->capacity < m->packets ? m->capacity : m->packets;
+  Ws w;
+  int rc = check_ws(ws, ws_bytes, cap, 1, &w);
+  if (rc) return rc;
+  Shapes sh;
+  resolve_tuning(nullptr, &sh);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(launch_fill32(w.at<uint32_t>(w.L.tickets), kMaxTickets, 0, s));
+  return enqueue_matrix_stats(w, sh, m, reinterpret_cast<uint64_t *>(out), s);
+}
+
+int ns_accumulate(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
+                  ns_matrix_t *acc_out, void *ws, uint64_t ws_bytes, void *stream) {
+  if (!acc_in || !win || !acc_out) return NS_ERR_INVALID_ARG;
+  if (sign != 1 && sign != -1) return NS_ERR_INVALID_ARG;
+  const ns_matrix_t *ins[2] = {acc_in, win};
+  for (const ns_matrix_t *m : ins) {
+    if (!m->keys || !m->counts || !m->nnz) return NS_ERR_INVALID_ARG;
+    if (m->keys == acc_out->keys || m->counts == acc_out->counts || m->nnz == acc_out->nnz ||
+        m->keys == acc_out->counts || m->counts == acc_out->keys)
+      return NS_ERR_INVALID_ARG;
+  }
+  if (!acc_out->keys || !acc_out->counts || !acc_out->nnz) return NS_ERR_INVALID_ARG;
+  const uint64_t na = acc_in->capacity < acc_in->packets ? acc_in->capacity : acc_in->packets;
+  const uint64_t nb = win->capacity < win->packets ? win->capacity : win->packets;
+  if (sign < 0 && win->packets > acc_in->packets) return NS_ERR_UNDERFLOW;
+  const uint64_t need = sign > 0 ? na + nb : na;
+  if (acc_out->capacity < need) return NS_ERR_CAPACITY;
+  Ws w;
+  int rc = check_ws(ws, ws_bytes, na + nb, 1, &w);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint64_t tiles = (na + nb) / kMergeTile + 2;
+  uint64_t *lbs = w.at<uint64_t>(w.L.lbs);
+  HIP_TRY(launch_fill32(w.at<uint32_t>(w.L.tickets), kMaxTickets, 0, s));
+  HIP_TRY(launch_fill64(lbs, tiles, 0, s));
+  MergeArgs a{};
+  a.ka = acc_in->keys;
+  a.ca = acc_in->counts;
+  a.na = acc_in->nnz;
+  a.kb = win->keys;
+  a.cb = win->counts;
+  a.nb = win->nnz;
+  a.na_max = na;
+  a.nb_max = nb;
+  a.kc = acc_out->keys;
+  a.cc = acc_out->counts;
+  a.nc = acc_out->nnz;
+  a.sign = sign;
+  a.lb = lbs;
+  a.ticket = w.ticket();
+  HIP_TRY(timed(K_MERGE, s, [&] { return launch_merge(a, tiles, s); }));
+  acc_out->packets = sign > 0 ? acc_in->packets + win->packets : acc_in->packets - win->packets;
+  return NS_OK;
+}
+
+int ns_batch_stats_eager(const uint32_t *src, const uint32_t *dst, const uint64_t *offsets,
+                         uint32_t num_windows, uint64_t total_packets, ns_stats_t *out,
+                         ns_matrix_t *agg_out, ns_stats_t *agg_stats,
+                         ns_batch_matrices_t *win_out, const ns_tuning_t *tune, void *ws,
+                         uint64_t ws_bytes, void *stream) {
+  BatchArgs b;
+  Ws w;
+  int rc = batch_checks(src, dst, offsets, num_windows, total_packets, out, agg_out, agg_stats,
+                        win_out, tune, ws, ws_bytes, &b, &w);
+  if (rc) return rc;
+  rc = enqueue_batch(b, w, static_cast<hipStream_t>(stream));
+  if (rc) return rc;
+  if (agg_out) agg_out->packets = total_packets;
+  return NS_OK;
+}
+
+int ns_batch_stats(const uint32_t *src, const uint32_t *dst, const uint64_t *offsets,
+                   uint32_t num_windows, uint64_t total_packets, ns_stats_t *out,
+                   ns_matrix_t *agg_out, ns_stats_t *agg_stats, ns_batch_matrices_t *win_out,
+                   const ns_tuning_t *tune, void *ws, uint64_t ws_bytes, void *stream) {
+  BatchArgs b;
+  Ws w;
+  int rc = batch_checks(src, dst, offsets, num_windows, total_packets, out, agg_out, agg_stats,
+                        win_out, tune, ws, ws_bytes, &b, &w);
+  if (rc) return rc;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return NS_ERR_HIP;
+  const std::string key = batch_key(dev, b, ws, ws_bytes);
+  GraphCache &c = cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  auto it = c.execs.find(key);
+  hipGraphExec_t exec = nullptr;
+  if (it != c.execs.end()) {
+    exec = it->second;
+  } else {
+    if (!c.capture[dev]) HIP_TRY(hipStreamCreateWithFlags(&c.capture[dev], hipStreamNonBlocking));
+    hipStream_t cs = c.capture[dev];
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_batch(b, w, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rc || e != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      return rc ? rc : NS_ERR_HIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ei != hipSuccess) return NS_ERR_HIP;
+    if (c.execs.size() >= 64) {
+      for (auto &kv : c.execs) hipGraphExecDestroy(kv.second);
+      c.execs.clear();
+    }
+    c.execs.emplace(key, exec);
+  }
+  HIP_TRY(hipGraphLaunch(exec, static_cast<hipStream_t>(stream)));
+  if (agg_out) agg_out->packets = total_packets;
+  return NS_OK;
+}
+
+int ns_device_status(void *stream, int *status) {
+  if (!status) return NS_ERR_INVALID_ARG;
+  HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  HIP_TRY(read_and_clear_status(status));
+  return NS_OK;
+}
+
+int ns_timing_enable(int on) {
+  Profiler &p = prof();
+  std::lock_guard<std::mutex> lock(p.mu);
+  p.on = on != 0;
+  return NS_OK;
+}
+
+int ns_timing_reset(void) {
+  Profiler &p = prof();
+  std::lock_guard<std::mutex> lock(p.mu);
+  for (auto &m : p.marks) {
+    hipEventDestroy(m.a);
+    hipEventDestroy(m.b);
+  }
+  p.marks.clear();
+  return NS_OK;
+}
+
+int ns_timing_read(uint32_t kind, double *total_ms, uint64_t *launches) {
+  if (!total_ms || !launches || kind >= K_COUNT) return NS_ERR_INVALID_ARG;
+  Profiler &p = prof();
+  std::lock_guard<std::mutex> lock(p.mu);
+  double t = 0;
+  uint64_t n = 0;
+  for (auto &m : p.marks) {
+    if ((uint32_t)m.kind != kind) continue;
+    HIP_TRY(hipEventSynchronize(m.b));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, m.a, m.b));
+    t += ms;
+    ++n;
+  }
+  *total_ms = t;
+  *launches = n;
+  return NS_OK;
+}
+
+int ns_release_graphs(void) {
+  GraphCache &c = cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  for (auto &kv : c.execs) hipGraphExecDestroy(kv.second);
+  c.execs.clear();
+  return NS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// Device-side building blocks shared by the libns kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ns {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Decoupled look-back words: status in the top two bits, value in the low 62.
+// A tile first publishes its own aggregate (AGG), then, once it knows the sum
+// of everything before it, its inclusive prefix (INC). Readers spin on a word
+// until its status is non-zero. Status and value share one 64-bit word, so a
+// relaxed agent-scope atomic is enough: no other data hangs on the flag.
+// Tiles are handed out by an atomic ticket, so every tile a reader waits on
+// belongs to a workgroup that is already running.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kLbAgg = 1ull << 62;
+constexpr uint64_t kLbInc = 2ull << 62;
+constexpr uint64_t kLbVal = (1ull << 62) - 1;
+
+__device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t lb_load(const uint64_t *p) {
+  return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of channel `chan` for tile t: sum of the aggregates of tiles
+// first..t-1, walking back until an inclusive prefix is found. `stride` is the
+// number of channels per tile.
+__device__ __forceinline__ uint64_t lb_walk(const uint64_t *lb, uint32_t stride, uint32_t chan,
+                                            uint32_t t, uint32_t first) {
+  uint64_t excl = 0;
+  for (int64_t j = (int64_t)t - 1; j >= (int64_t)first; --j) {
+    const uint64_t *p = lb + (uint64_t)j * stride + chan;
+    uint64_t v = lb_load(p);
+    while ((v >> 62) == 0) {
+      __builtin_amdgcn_s_sleep(1);
+      v = lb_load(p);
+    }
+    excl += v & kLbVal;
+    if ((v >> 62) == 2) break;
+  }
+  return excl;
+}
+
+// ---------------------------------------------------------------------------
+// wave / block helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+// number of set bits of m in lanes below this one
+__device__ __forceinline__ uint32_t count_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    uint64_t y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_max(uint64_t x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    uint64_t y = __shfl_xor(x, o, kWave);
+    x = x > y ? x : y;
+  }
+  return x;
+}
+
+// Block-wide exclusive scan of one u64 per thread. s_tmp holds BLOCK/64
+// entries. Returns the thread's exclusive prefix; *total = block sum.
+template <int BLOCK>
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *s_tmp, uint64_t *total) {
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const uint64_t x = wave_incl_scan(v);
+  if (lane == kWave - 1) s_tmp[wv] = x;
+  __syncthreads();
+  uint64_t pre = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < BLOCK / kWave; ++q) {
+    const uint64_t s = s_tmp[q];
+    pre += (q < wv) ? s : 0;
+    tot += s;
+  }
+  *total = tot;
+  __syncthreads();
+  return pre + x - v;
+}
+
+// index of the segment that owns tile t: the last w with tile_off[w] <= t
+// (empty segments own no tiles, so this is never an empty one)
+__device__ __forceinline__ uint32_t find_owner(const uint64_t *off, uint32_t W, uint64_t t) {
+  uint32_t lo = 0, hi = W;  // answer in [0, W)
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint64_t pack_key(uint32_t s, uint32_t d) {
+  return ((uint64_t)s << 32) | (uint64_t)d;
+}
+
+}  // namespace ns

@@ -1,0 +1,976 @@
+// HIP kernels of libns (gfx950, wave64): radix sort of packed (src,dst) keys,
+// run-length encoding into a sorted COO traffic matrix, row and column run
+// reductions for the eight quantities, and merge-path union-add.
+//
+// Every kernel that walks a data-dependent number of tiles is persistent: the
+// grid is sized to what fits on the device, tiles are handed out by an atomic
+// ticket, and the tile count is read from device memory. That makes the whole
+// sequence capturable in one HIP graph and keeps the look-back waits safe
+// (a waited-on tile always belongs to a running workgroup).
+#include "ns_device.h"
+#include "ns_launch.h"
+
+namespace ns {
+
+__device__ int g_status;  // NS_OK (0) or NS_ERR_UNDERFLOW (-5), set by the merge
+
+// ---------------------------------------------------------------------------
+// small utilities
+// ---------------------------------------------------------------------------
+__global__ void k_fill64(uint64_t *p, uint64_t n, uint64_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill32(uint32_t *p, uint64_t n, uint32_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// seg = {0, n}, with n read from the device when n_dev is given and clamped to
+// the host-known bound `n` (a device count never drives accesses past it)
+__global__ void k_seg1(uint64_t *seg, const uint64_t *n_dev, uint64_t n) {
+  if (threadIdx.x == 0) {
+    seg[0] = 0;
+    seg[1] = n_dev ? min(*n_dev, n) : n;
+  }
+}
+
+// Tile prefix per segment for up to three tile sizes, one workgroup.
+__global__ __launch_bounds__(1024) void k_tiles(const uint64_t *seg_off, uint32_t W, uint32_t ta,
+                                                uint64_t *oa, uint32_t tb, uint64_t *ob,
+                                                uint32_t tc, uint64_t *oc) {
+  __shared__ uint64_t s_tmp[16];
+  uint64_t ca = 0, cb = 0, cc = 0;
+  for (uint32_t base = 0; base < W; base += 1024) {
+    const uint32_t w = base + threadIdx.x;
+    const uint64_t len = (w < W) ? seg_off[w + 1] - seg_off[w] : 0;
+    uint64_t tot;
+    if (oa) {
+      const uint64_t x = block_excl_scan<1024>((len + ta - 1) / ta, s_tmp, &tot);
+      if (w < W) oa[w] = ca + x;
+      ca += tot;
+    }
+    if (ob) {
+      const uint64_t x = block_excl_scan<1024>((len + tb - 1) / tb, s_tmp, &tot);
+      if (w < W) ob[w] = cb + x;
+      cb += tot;
+    }
+    if (oc) {
+      const uint64_t x = block_excl_scan<1024>((len + tc - 1) / tc, s_tmp, &tot);
+      if (w < W) oc[w] = cc + x;
+      cc += tot;
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (oa) oa[W] = ca;
+    if (ob) ob[W] = cb;
+    if (oc) oc[W] = cc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Radix sort, step 1: byte-digit histograms of every key, per segment.
+// Digit p of key src<<32|dst is bits [8p, 8p+8): p<4 come from dst, p>=4 from
+// src. LDS counters per workgroup, flushed with one atomic per non-zero bin.
+// ---------------------------------------------------------------------------
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_hist_packets(const uint32_t *__restrict__ src,
+                                                        const uint32_t *__restrict__ dst,
+                                                        const uint64_t *seg_off,
+                                                        const uint64_t *tile_off, uint32_t W,
+                                                        uint32_t *hist) {
+  __shared__ uint32_t s_h[kKeyDigits * kBins];
+  const uint64_t total = tile_off[W];
+  for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    for (int i = threadIdx.x; i < kKeyDigits * kBins; i += BLOCK) s_h[i] = 0;
+    __syncthreads();
+    const uint32_t w = find_owner(tile_off, W, t);
+    const uint64_t start = seg_off[w] + (t - tile_off[w]) * (uint64_t)kHistTile;
+    const uint64_t end = min(start + (uint64_t)kHistTile, seg_off[w + 1]);
+    for (uint64_t i = start + threadIdx.x; i < end; i += BLOCK) {
+      const uint32_t d = dst[i], s = src[i];
+      atomicAdd(&s_h[0 * kBins + (d & 255)], 1u);
+      atomicAdd(&s_h[1 * kBins + ((d >> 8) & 255)], 1u);
+      atomicAdd(&s_h[2 * kBins + ((d >> 16) & 255)], 1u);
+      atomicAdd(&s_h[3 * kBins + (d >> 24)], 1u);
+      atomicAdd(&s_h[4 * kBins + (s & 255)], 1u);
+      atomicAdd(&s_h[5 * kBins + ((s >> 8) & 255)], 1u);
+      atomicAdd(&s_h[6 * kBins + ((s >> 16) & 255)], 1u);
+      atomicAdd(&s_h[7 * kBins + (s >> 24)], 1u);
+    }
+    __syncthreads();
+    uint32_t *g = hist + (uint64_t)w * (kKeyDigits * kBins);
+    for (int i = threadIdx.x; i < kKeyDigits * kBins; i += BLOCK) {
+      const uint32_t c = s_h[i];
+      if (c) atomicAdd(&g[i], c);
+    }
+    __syncthreads();
+  }
+}
+
+// Radix sort, step 2: exclusive scan of each 256-bin row (one wave per row).
+__global__ __launch_bounds__(256) void k_hist_scan(const uint32_t *hist, uint32_t *base,
+                                                   uint64_t rows) {
+  const uint64_t row = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (row >= rows) return;  // whole wave leaves together
+  const uint32_t *h = hist + row * kBins;
+  const uint32_t v0 = h[lane * 4 + 0], v1 = h[lane * 4 + 1], v2 = h[lane * 4 + 2],
+                 v3 = h[lane * 4 + 3];
+  const uint64_t mine = (uint64_t)v0 + v1 + v2 + v3;
+  const uint64_t x = wave_incl_scan(mine) - mine;
+  uint32_t *b = base + row * kBins;
+  b[lane * 4 + 0] = (uint32_t)x;
+  b[lane * 4 + 1] = (uint32_t)(x + v0);
+  b[lane * 4 + 2] = (uint32_t)(x + v0 + v1);
+  b[lane * 4 + 3] = (uint32_t)(x + v0 + v1 + v2);
+}
+
+// ---------------------------------------------------------------------------
+// Radix sort, step 3: one stable counting pass on one byte digit, segment by
+// segment (each key moves only within its own segment).
+//
+// A tile of BLOCK*ITEMS keys is loaded wave-striped (coalesced). Each wave
+// ranks its keys stably with ballot peer masks: lanes holding the same digit
+// find each other with 8 ballots, and the lowest such lane updates the wave's
+// LDS counter for that digit, so a hot (Zipf) digit costs one LDS update per
+// wave, not per lane. Per-wave counts are combined into the tile's digit
+// totals, which are published for decoupled look-back; each of 256 threads
+// then resolves the prefix of one digit from the preceding tiles of the same
+// segment. Keys are scattered into LDS in digit order and written out from
+// there, so consecutive threads write consecutive addresses within a digit.
+// ---------------------------------------------------------------------------
+template <int BLOCK, int ITEMS, bool PACKETS>
+__global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
+  constexpr int TILE = BLOCK * ITEMS;
+  constexpr int NW = BLOCK / kWave;
+  static_assert(BLOCK >= kBins, "one thread per digit");
+  __shared__ uint64_t s_keys[TILE];
+  __shared__ uint32_t s_wcnt[NW][kBins];
+  __shared__ uint32_t s_tot[kBins];
+  __shared__ uint32_t s_lstart[kBins];
+  __shared__ uint64_t s_gbase[kBins];
+  __shared__ uint32_t s_tile;
+
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const uint64_t total = a.tile_off[a.W];
+  const uint32_t shift = a.shift;
+
+  for (;;) {
+    if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
+    for (int i = tid; i < NW * kBins; i += BLOCK) (&s_wcnt[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t t = s_tile;
+    if (t >= total) break;
+    const uint32_t w = find_owner(a.tile_off, a.W, t);
+    const uint32_t first = (uint32_t)a.tile_off[w];
+    const uint64_t seg_lo = a.seg_off[w];
+    const uint64_t start = seg_lo + (uint64_t)(t - first) * TILE;
+    const uint32_t n = (uint32_t)min((uint64_t)TILE, a.seg_off[w + 1] - start);
+
+    uint64_t key[ITEMS];
+    uint32_t dig[ITEMS];
+    uint32_t rank[ITEMS];
+    const uint32_t wbase = wv * (kWave * ITEMS);
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t li = wbase + k * kWave + lane;
+      uint64_t x = 0;
+      if (li < n) {
+        if (PACKETS) x = pack_key(a.src[start + li], a.dst[start + li]);
+        else x = a.in[start + li];
+      }
+      key[k] = x;
+      dig[k] = (li < n) ? (uint32_t)(x >> shift) & 255u : kBins;
+    }
+    // stable rank within the wave, in (k, lane) order = original order
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t d = dig[k];
+      const bool valid = d < kBins;
+      uint64_t peers = ballot64(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = ballot64(bit);
+        peers &= bit ? m : ~m;
+      }
+      if (valid) {
+        const uint32_t below = count_below(peers);
+        const uint32_t old = s_wcnt[wv][d];
+        rank[k] = old + below;
+        if (below == 0) s_wcnt[wv][d] = old + (uint32_t)__popcll(peers);
+      }
+    }
+    __syncthreads();
+    if (tid < kBins) {
+      uint32_t sum = 0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) {
+        const uint32_t c = s_wcnt[q][tid];
+        s_wcnt[q][tid] = sum;
+        sum += c;
+      }
+      s_tot[tid] = sum;
+      // publish this tile's digit counts as early as possible
+      uint64_t *row = a.lb + (uint64_t)t * kBins;
+      lb_store(row + tid, (t == first ? kLbInc : kLbAgg) | sum);
+    }
+    __syncthreads();
+    if (tid < kWave) {  // exclusive scan of the 256 digit totals, 4 per lane
+      const uint32_t v0 = s_tot[tid * 4], v1 = s_tot[tid * 4 + 1], v2 = s_tot[tid * 4 + 2],
+                     v3 = s_tot[tid * 4 + 3];
+      const uint64_t mine = (uint64_t)v0 + v1 + v2 + v3;
+      const uint32_t x = (uint32_t)(wave_incl_scan(mine) - mine);
+      s_lstart[tid * 4] = x;
+      s_lstart[tid * 4 + 1] = x + v0;
+      s_lstart[tid * 4 + 2] = x + v0 + v1;
+      s_lstart[tid * 4 + 3] = x + v0 + v1 + v2;
+    }
+    if (tid < kBins) {
+      uint64_t excl = 0;
+      if (t != first) {
+        excl = lb_walk(a.lb, kBins, tid, t, first);
+        lb_store(a.lb + (uint64_t)t * kBins + tid, kLbInc | (excl + s_tot[tid]));
+      }
+      s_gbase[tid] = seg_lo + a.base[(uint64_t)w * a.base_stride + tid] + excl;
+      a.lb_next[(uint64_t)t * kBins + tid] = 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t d = dig[k];
+      if (d < kBins) s_keys[s_lstart[d] + s_wcnt[wv][d] + rank[k]] = key[k];
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += BLOCK) {
+      const uint64_t x = s_keys[i];
+      const uint32_t d = (uint32_t)(x >> shift) & 255u;
+      a.out[s_gbase[d] + (i - s_lstart[d])] = x;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// First index in (lo, hi] whose key differs from K, given keys[lo] == K and a
+// sorted array: galloping then bisection, O(log run length) reads.
+// ---------------------------------------------------------------------------
+__device__ uint64_t run_end(const uint64_t *keys, uint64_t lo, uint64_t hi, uint64_t K) {
+  uint64_t step = 1;
+  while (lo + step < hi && keys[lo + step] == K) {
+    lo += step;
+    step <<= 1;
+  }
+  uint64_t r = min(lo + step, hi);
+  while (r - lo > 1) {
+    const uint64_t mid = lo + (r - lo) / 2;
+    if (keys[mid] == K) lo = mid; else r = mid;
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Run-length encoding of sorted packet keys, with row heads.
+// A link head is a position whose key differs from its predecessor in the
+// segment (Table I: unique links = nonzeros of A); a row head is one whose
+// source differs (unique sources). Link and row heads are compacted over the
+// whole launch with a two-channel decoupled look-back, so every window's links
+// land at [link_off[w], link_off[w+1]). Each link's count is the distance to
+// the next link head (in the tile, or found by a galloping search past the tile
+// end for the last run). Each row head records its packet position and link
+// index; differences of consecutive row heads give per-source packets and
+// fan-out. May run in place (ukeys == keys): a tile finishes every read beyond
+// its end before it publishes, and later tiles write only after that.
+// ---------------------------------------------------------------------------
+template <int ITEMS>
+__global__ __launch_bounds__(256) void k_rle(RleArgs a) {
+  constexpr int BLOCK = 256;
+  constexpr int TILE = BLOCK * ITEMS;
+  static_assert(ITEMS <= 32, "head masks are 32-bit");
+  __shared__ uint64_t s_k[TILE + 1];
+  __shared__ uint32_t s_hpos[TILE];
+  __shared__ uint32_t s_rpos[TILE];
+  __shared__ uint32_t s_rlr[TILE];
+  __shared__ uint32_t s_ch[kColDigits * kBins];
+  __shared__ uint64_t s_tmp[BLOCK / kWave];
+  __shared__ uint64_t s_L0, s_R0, s_trail;
+  __shared__ uint32_t s_tile;
+
+  const int tid = threadIdx.x;
+  const uint64_t total = a.tile_off[a.W];
+  for (;;) {
+    if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
+    if (a.col_hist)
+      for (int i = tid; i < kColDigits * kBins; i += BLOCK) s_ch[i] = 0;
+    __syncthreads();
+    const uint32_t t = s_tile;
+    if (t >= total) break;
+    const uint32_t w = find_owner(a.tile_off, a.W, t);
+    const uint32_t first = (uint32_t)a.tile_off[w];
+    const uint64_t seg_lo = a.seg_off[w], seg_hi = a.seg_off[w + 1];
+    const uint64_t start = seg_lo + (uint64_t)(t - first) * TILE;
+    const uint32_t n = (uint32_t)min((uint64_t)TILE, seg_hi - start);
+
+    for (uint32_t i = tid; i < n; i += BLOCK) s_k[1 + i] = a.keys[start + i];
+    if (tid == 0) {
+      // predecessor of the tile's first key; at a segment start, a value that
+      // differs from it in both halves so that position is a link and row head
+      s_k[0] = (start > seg_lo) ? a.keys[start - 1] : (a.keys[start] ^ 0xFFFFFFFF00000001ull);
+    }
+    __syncthreads();
+
+    uint32_t lmask = 0, rmask = 0;
+    const uint32_t p0 = tid * ITEMS;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t p = p0 + k;
+      if (p < n) {
+        const uint64_t cur = s_k[1 + p], prev = s_k[p];
+        lmask |= (uint32_t)(cur != prev) << k;
+        rmask |= (uint32_t)((cur >> 32) != (prev >> 32)) << k;
+      }
+    }
+    uint64_t tot;
+    const uint64_t x = block_excl_scan<BLOCK>(((uint64_t)__popc(rmask) << 32) | __popc(lmask),
+                                              s_tmp, &tot);
+    const uint32_t xl = (uint32_t)x, xr = (uint32_t)(x >> 32);
+    const uint32_t TL = (uint32_t)tot, TR = (uint32_t)(tot >> 32);
+    {
+      uint32_t jl = xl, jr = xr;
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        if (rmask & (1u << k)) {
+          s_rpos[jr] = p0 + k;
+          s_rlr[jr] = jl;  // a row head is also a link head: its link rank
+          ++jr;
+        }
+        if (lmask & (1u << k)) s_hpos[jl++] = p0 + k;
+      }
+    }
+    if (tid == 0) {
+      uint64_t e = start + n;
+      if (TL > 0 && e < seg_hi) {
+        const uint64_t K = s_k[n];
+        if (a.keys[e] == K) e = run_end(a.keys, e, seg_hi, K);
+      }
+      s_trail = e;
+    }
+    __syncthreads();  // the search above is done before anything is published
+    if (tid < 2) {
+      const uint64_t mine = tid == 0 ? TL : TR;
+      uint64_t *slot = a.lb + 2ull * t + tid;
+      uint64_t excl = 0;
+      if (t == 0) {
+        lb_store(slot, kLbInc | mine);
+      } else {
+        lb_store(slot, kLbAgg | mine);
+        excl = lb_walk(a.lb, 2, tid, t, 0);
+        lb_store(slot, kLbInc | (excl + mine));
+      }
+      if (tid == 0) s_L0 = excl; else s_R0 = excl;
+    }
+    __syncthreads();
+    const uint64_t L0 = s_L0, R0 = s_R0, trail = s_trail;
+    if (tid == 0) {
+      if (t == first) {
+        a.link_off[w] = L0;
+        a.row_off[w] = R0;
+        for (int64_t v = (int64_t)w - 1; v >= 0 && a.seg_off[v] == a.seg_off[v + 1]; --v) {
+          a.link_off[v] = L0;
+          a.row_off[v] = R0;
+        }
+      }
+      if (t == total - 1) {
+        const uint64_t Le = L0 + TL, Re = R0 + TR;
+        for (uint32_t v = w + 1; v <= a.W; ++v) {
+          a.link_off[v] = Le;
+          a.row_off[v] = Re;
+        }
+        if (a.rpos) {
+          a.rpos[Re] = a.seg_off[a.W];
+          a.rlink[Re] = Le;
+        }
+        if (a.nnz_out) *a.nnz_out = Le;
+      }
+    }
+    for (uint32_t r = tid; r < TL; r += BLOCK) {
+      const uint32_t p = s_hpos[r];
+      const uint64_t K = s_k[1 + p];
+      const uint64_t e = (r + 1 < TL) ? start + s_hpos[r + 1] : trail;
+      const uint64_t cnt = e - (start + p);
+      const uint64_t L = L0 + r;
+      if (a.ukeys) a.ukeys[L] = K;
+      if (a.counts) a.counts[L] = cnt;
+      if (a.items) a.items[L] = (K << 32) | cnt;
+      if (a.col_hist) {
+        const uint32_t d = (uint32_t)K;
+        atomicAdd(&s_ch[0 * kBins + (d & 255)], 1u);
+        atomicAdd(&s_ch[1 * kBins + ((d >> 8) & 255)], 1u);
+        atomicAdd(&s_ch[2 * kBins + ((d >> 16) & 255)], 1u);
+        atomicAdd(&s_ch[3 * kBins + (d >> 24)], 1u);
+      }
+    }
+    if (a.rpos) {
+      for (uint32_t q = tid; q < TR; q += BLOCK) {
+        a.rpos[R0 + q] = start + s_rpos[q];
+        a.rlink[R0 + q] = L0 + s_rlr[q];
+      }
+    }
+    __syncthreads();
+    if (a.col_hist) {
+      uint32_t *g = a.col_hist + (uint64_t)w * (kColDigits * kBins);
+      for (int i = tid; i < kColDigits * kBins; i += BLOCK) {
+        const uint32_t c = s_ch[i];
+        if (c) atomicAdd(&g[i], c);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Run reduction over a sorted array with explicit values.
+// mode 0 (rows of a matrix): group = source, value = A(i,j); every link also
+//   emits its column item dst<<32|count and the item's digit histograms.
+// mode 1 (columns): group = destination of a sorted column item, value = the
+//   item's count.
+// Heads are compacted with a two-channel look-back (heads, value prefix); each
+// head stores its position and the exclusive value prefix, so consecutive
+// heads give run length (fan-out / fan-in) and run sum (packets).
+// ---------------------------------------------------------------------------
+template <int ITEMS, int MODE>
+__global__ __launch_bounds__(256) void k_runs(RunArgs a) {
+  constexpr int BLOCK = 256;
+  constexpr int TILE = BLOCK * ITEMS;
+  __shared__ uint64_t s_g[TILE + 1];   // group key
+  __shared__ uint32_t s_v[TILE];       // value (< 2^32)
+  __shared__ uint32_t s_hp[TILE];      // head local positions
+  __shared__ uint32_t s_hv[TILE];      // tile-local exclusive value prefix at head
+  __shared__ uint32_t s_ch[kColDigits * kBins];
+  __shared__ uint64_t s_tmp[BLOCK / kWave];
+  __shared__ uint64_t s_H0, s_V0;
+  __shared__ uint32_t s_tile;
+
+  const int tid = threadIdx.x;
+  const uint64_t total = a.tile_off[a.W];
+  for (;;) {
+    if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
+    if (MODE == 0 && a.col_hist)
+      for (int i = tid; i < kColDigits * kBins; i += BLOCK) s_ch[i] = 0;
+    __syncthreads();
+    const uint32_t t = s_tile;
+    if (t >= total) break;
+    const uint32_t w = find_owner(a.tile_off, a.W, t);
+    const uint32_t first = (uint32_t)a.tile_off[w];
+    const uint64_t seg_lo = a.seg_off[w], seg_hi = a.seg_off[w + 1];
+    const uint64_t start = seg_lo + (uint64_t)(t - first) * TILE;
+    const uint32_t n = (uint32_t)min((uint64_t)TILE, seg_hi - start);
+
+    for (uint32_t i = tid; i < n; i += BLOCK) {
+      const uint64_t k = a.keys[start + i];
+      s_g[1 + i] = k >> 32;
+      if (MODE == 0) {
+        const uint64_t c = a.counts[start + i];
+        s_v[i] = (uint32_t)c;
+        if (a.items) a.items[start + i] = (k << 32) | c;
+        if (a.col_hist) {
+          const uint32_t d = (uint32_t)k;
+          atomicAdd(&s_ch[0 * kBins + (d & 255)], 1u);
+          atomicAdd(&s_ch[1 * kBins + ((d >> 8) & 255)], 1u);
+          atomicAdd(&s_ch[2 * kBins + ((d >> 16) & 255)], 1u);
+          atomicAdd(&s_ch[3 * kBins + (d >> 24)], 1u);
+        }
+      } else {
+        s_v[i] = (uint32_t)k;
+      }
+    }
+    if (tid == 0) s_g[0] = (start > seg_lo) ? (a.keys[start - 1] >> 32) : ~0ull;
+    __syncthreads();
+
+    uint32_t hmask = 0, vsum = 0;
+    const uint32_t p0 = tid * ITEMS;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t p = p0 + k;
+      if (p < n) {
+        hmask |= (uint32_t)(s_g[1 + p] != s_g[p]) << k;
+        vsum += s_v[p];
+      }
+    }
+    uint64_t tot;
+    const uint64_t x = block_excl_scan<BLOCK>(((uint64_t)__popc(hmask) << 32) | vsum, s_tmp, &tot);
+    const uint32_t xv = (uint32_t)x, xh = (uint32_t)(x >> 32);
+    const uint32_t TV = (uint32_t)tot, TH = (uint32_t)(tot >> 32);
+    {
+      uint32_t jh = xh, run = xv;
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t p = p0 + k;
+        if (hmask & (1u << k)) {
+          s_hp[jh] = p;
+          s_hv[jh] = run;
+          ++jh;
+        }
+        if (p < n) run += s_v[p];
+      }
+    }
+    if (tid < 2) {
+      const uint64_t mine = tid == 0 ? TH : TV;
+      uint64_t *slot = a.lb + 2ull * t + tid;
+      uint64_t excl = 0;
+      if (t == 0) {
+        lb_store(slot, kLbInc | mine);
+      } else {
+        lb_store(slot, kLbAgg | mine);
+        excl = lb_walk(a.lb, 2, tid, t, 0);
+        lb_store(slot, kLbInc | (excl + mine));
+      }
+      if (tid == 0) s_H0 = excl; else s_V0 = excl;
+    }
+    __syncthreads();
+    const uint64_t H0 = s_H0, V0 = s_V0;
+    if (tid == 0) {
+      if (t == first) {
+        a.head_off[w] = H0;
+        for (int64_t v = (int64_t)w - 1; v >= 0 && a.seg_off[v] == a.seg_off[v + 1]; --v)
+          a.head_off[v] = H0;
+      }
+      if (t == total - 1) {
+        const uint64_t He = H0 + TH;
+        for (uint32_t v = w + 1; v <= a.W; ++v) a.head_off[v] = He;
+        a.hpos[He] = a.seg_off[a.W];
+        a.hval[He] = V0 + TV;
+      }
+    }
+    for (uint32_t h = tid; h < TH; h += BLOCK) {
+      a.hpos[H0 + h] = start + s_hp[h];
+      a.hval[H0 + h] = V0 + s_hv[h];
+    }
+    __syncthreads();
+    if (MODE == 0 && a.col_hist) {
+      uint32_t *g = a.col_hist + (uint64_t)w * (kColDigits * kBins);
+      for (int i = tid; i < kColDigits * kBins; i += BLOCK) {
+        const uint32_t c = s_ch[i];
+        if (c) atomicAdd(&g[i], c);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-segment maxima of consecutive-head differences (DPP-style wave max,
+// then one 64-bit atomic per wave; per-lane atomics only where a wave
+// straddles a segment boundary).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_segmax(const uint64_t *a, const uint64_t *b,
+                                                const uint64_t *head_off, uint32_t W,
+                                                uint64_t *stats, int fa, int fb) {
+  const uint64_t total = head_off[W];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < total; base += stride) {
+    const uint64_t r = base + threadIdx.x;
+    const bool valid = r < total;
+    uint32_t w = 0;
+    uint64_t da = 0, db = 0;
+    if (valid) {
+      w = find_owner(head_off, W, r);
+      da = a[r + 1] - a[r];
+      db = b[r + 1] - b[r];
+    }
+    const uint64_t vm = ballot64(valid);
+    const int lead = __ffsll((long long)vm) - 1;  // lowest valid lane (vm != 0 here)
+    const uint32_t w0 = __shfl(w, lead, kWave);
+    if (ballot64(valid && w == w0) == vm) {
+      const uint64_t ma = wave_max(da), mb = wave_max(db);
+      if ((threadIdx.x & (kWave - 1)) == (uint32_t)lead) {
+        atomicMax((unsigned long long *)&stats[(uint64_t)w0 * 8 + fa], (unsigned long long)ma);
+        atomicMax((unsigned long long *)&stats[(uint64_t)w0 * 8 + fb], (unsigned long long)mb);
+      }
+    } else if (valid) {
+      atomicMax((unsigned long long *)&stats[(uint64_t)w * 8 + fa], (unsigned long long)da);
+      atomicMax((unsigned long long *)&stats[(uint64_t)w * 8 + fb], (unsigned long long)db);
+    }
+  }
+}
+
+__global__ void k_finalize(const uint64_t *seg_off, const uint64_t *link_off,
+                           const uint64_t *row_off, const uint64_t *col_off, uint32_t W,
+                           uint64_t *stats) {
+  for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < W; w += gridDim.x * blockDim.x) {
+    uint64_t *s = stats + (uint64_t)w * 8;
+    s[0] = seg_off[w + 1] - seg_off[w];
+    s[1] = link_off[w + 1] - link_off[w];
+    s[2] = row_off[w + 1] - row_off[w];
+    s[3] = col_off[w + 1] - col_off[w];
+  }
+}
+
+// Matrix totals: with row_hval, valid packets (the row pass's value sentinel =
+// sum of all counts), unique links and unique sources; with col_off, unique
+// destinations.
+__global__ void k_finalize_matrix(const uint64_t *row_hval, const uint64_t *row_off,
+                                  const uint64_t *col_off, const uint64_t *nnz, uint64_t *stats) {
+  if (threadIdx.x == 0) {
+    if (row_hval) {
+      stats[0] = row_hval[row_off[1]];
+      stats[1] = *nnz;
+      stats[2] = row_off[1];
+    }
+    if (col_off) stats[3] = col_off[1];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Union-add / subtract of two sorted COO matrices by merge path.
+// Merged order puts A's entry before B's on equal keys, so equal keys are
+// adjacent: the A entry absorbs B's count (plus or minus) and the B entry is
+// dropped; for subtraction, entries that reach zero are dropped and a B entry
+// without a matching, large-enough A entry raises the device error word.
+// Kept entries are compacted with a one-channel look-back.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t merge_split(const uint64_t *A, uint64_t na, const uint64_t *B,
+                                                uint64_t nb, uint64_t d) {
+  uint64_t lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (A[mid] <= B[d - mid - 1]) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
+  constexpr int BLOCK = 256, ITEMS = 8, TILE = BLOCK * ITEMS;
+  __shared__ uint64_t s_k[TILE];
+  __shared__ uint64_t s_c[TILE];
+  __shared__ uint64_t s_tmp[BLOCK / kWave];
+  __shared__ uint64_t s_i0, s_i1, s_L0;
+  __shared__ uint64_t s_prevA, s_nextB, s_nextBc;
+  __shared__ int s_hasPrevA, s_hasNextB;
+  __shared__ uint32_t s_tile;
+
+  const int tid = threadIdx.x;
+  const uint64_t na = min(*a.na, a.na_max), nb = min(*a.nb, a.nb_max), ntot = na + nb;
+  const uint64_t tiles = (ntot + TILE - 1) / TILE;
+  if (ntot == 0) {
+    if (blockIdx.x == 0 && tid == 0) *a.nc = 0;
+    return;
+  }
+  for (;;) {
+    if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
+    __syncthreads();
+    const uint32_t t = s_tile;
+    if (t >= tiles) break;
+    const uint64_t d0 = (uint64_t)t * TILE, d1 = min(d0 + TILE, ntot);
+    if (tid == 0) s_i0 = merge_split(a.ka, na, a.kb, nb, d0);
+    if (tid == kWave) s_i1 = merge_split(a.ka, na, a.kb, nb, d1);
+    __syncthreads();
+    const uint64_t i0 = s_i0, i1 = s_i1, j0 = d0 - i0, j1 = d1 - i1;
+    const uint32_t la = (uint32_t)(i1 - i0), lb = (uint32_t)(j1 - j0);
+    for (uint32_t i = tid; i < la; i += BLOCK) {
+      s_k[i] = a.ka[i0 + i];
+      s_c[i] = a.ca[i0 + i];
+    }
+    for (uint32_t i = tid; i < lb; i += BLOCK) {
+      s_k[la + i] = a.kb[j0 + i];
+      s_c[la + i] = a.cb[j0 + i];
+    }
+    if (tid == 0) {
+      s_hasPrevA = i0 > 0;
+      s_prevA = i0 > 0 ? a.ka[i0 - 1] : 0;
+      s_hasNextB = j1 < nb;
+      s_nextB = j1 < nb ? a.kb[j1] : 0;
+      s_nextBc = j1 < nb ? a.cb[j1] : 0;
+    }
+    __syncthreads();
+    const uint64_t *sa = s_k, *sca = s_c, *sb = s_k + la, *scb = s_c + la;
+    // this thread's share of the tile's merged positions
+    const uint32_t dd0 = min((uint32_t)(tid * ITEMS), la + lb);
+    const uint32_t dd1 = min((uint32_t)((tid + 1) * ITEMS), la + lb);
+    uint32_t ia;
+    {
+      uint32_t lo = dd0 > lb ? dd0 - lb : 0, hi = dd0 < la ? dd0 : la;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (sa[mid] <= sb[dd0 - mid - 1]) lo = mid + 1; else hi = mid;
+      }
+      ia = lo;
+    }
+    uint32_t ib = dd0 - ia;
+    uint64_t ok[ITEMS], oc[ITEMS];
+    uint32_t kmask = 0;
+    bool underflow = false;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      ok[k] = 0;
+      oc[k] = 0;
+      if (dd0 + k < dd1) {
+        const bool takeA = ib >= lb || (ia < la && sa[ia] <= sb[ib]);
+        if (takeA) {
+          const uint64_t key = sa[ia], c = sca[ia];
+          bool hasB;
+          uint64_t bk, bc;
+          if (ib < lb) {
+            hasB = true;
+            bk = sb[ib];
+            bc = scb[ib];
+          } else {
+            hasB = s_hasNextB;
+            bk = s_nextB;
+            bc = s_nextBc;
+          }
+          const bool matched = hasB && bk == key;
+          uint64_t out = c;
+          if (matched) {
+            if (a.sign > 0) {
+              out = c + bc;
+            } else if (bc > c) {
+              underflow = true;
+              out = 0;
+            } else {
+              out = c - bc;
+            }
+          }
+          if (out != 0) {
+            ok[k] = key;
+            oc[k] = out;
+            kmask |= 1u << k;
+          }
+          ++ia;
+        } else {
+          const uint64_t key = sb[ib], c = scb[ib];
+          const bool hasA = ia > 0 || s_hasPrevA;
+          const uint64_t ak = ia > 0 ? sa[ia - 1] : s_prevA;
+          if (!(hasA && ak == key)) {  // unmatched B entry
+            if (a.sign > 0) {
+              ok[k] = key;
+              oc[k] = c;
+              kmask |= 1u << k;
+            } else {
+              underflow = true;
+            }
+          }
+          ++ib;
+        }
+      }
+    }
+    const uint32_t keep = __popc(kmask);
+    if (underflow) atomicOr(&g_status, 1);
+    uint64_t tot;
+    const uint64_t x = block_excl_scan<BLOCK>(keep, s_tmp, &tot);
+    if (tid == 0) {
+      uint64_t *slot = a.lb + t;
+      uint64_t excl = 0;
+      if (t == 0) {
+        lb_store(slot, kLbInc | tot);
+      } else {
+        lb_store(slot, kLbAgg | tot);
+        excl = lb_walk(a.lb, 1, 0, t, 0);
+        lb_store(slot, kLbInc | (excl + tot));
+      }
+      s_L0 = excl;
+      if (t == tiles - 1) *a.nc = excl + tot;
+    }
+    __syncthreads();  // everyone is done reading s_k / s_c
+    {
+      uint32_t pos = (uint32_t)x;
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        if (kmask & (1u << k)) {
+          s_k[pos] = ok[k];
+          s_c[pos] = oc[k];
+          ++pos;
+        }
+      }
+    }
+    __syncthreads();
+    const uint64_t L0 = s_L0;
+    for (uint32_t i = tid; i < tot; i += BLOCK) {
+      a.kc[L0 + i] = s_k[i];
+      a.cc[L0 + i] = s_c[i];
+    }
+    __syncthreads();
+  }
+}
+
+// ===========================================================================
+// host launchers
+// ===========================================================================
+namespace {
+
+int device_id() {
+  int d = 0;
+  hipGetDevice(&d);
+  return d;
+}
+
+int cu_count() {
+  static int cus[64] = {0};
+  const int d = device_id();
+  if (d < 64 && cus[d]) return cus[d];
+  int v = 0;
+  hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, d);
+  if (v <= 0) v = 256;
+  if (d < 64) cus[d] = v;
+  return v;
+}
+
+// resident workgroups of `fn` at `block` threads on the current device
+template <typename F>
+uint64_t resident(F fn, int block) {
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, block, 0) != hipSuccess || per <= 0)
+    per = 1;
+  return (uint64_t)per * cu_count();
+}
+
+uint32_t clamp_grid(uint64_t want, uint64_t cap) {
+  uint64_t g = want < cap ? want : cap;
+  if (g == 0) g = 1;
+  return (uint32_t)g;
+}
+
+}  // namespace
+
+hipError_t launch_fill64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint32_t g = clamp_grid((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill64, dim3(g), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint32_t g = clamp_grid((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill32, dim3(g), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg1(uint64_t *seg, const uint64_t *n_dev, uint64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg1, dim3(1), dim3(64), 0, s, seg, n_dev, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_tiles(const uint64_t *seg_off, uint32_t W, uint32_t ta, uint64_t *oa,
+                        uint32_t tb, uint64_t *ob, uint32_t tc, uint64_t *oc, hipStream_t s) {
+  hipLaunchKernelGGL(k_tiles, dim3(1), dim3(1024), 0, s, seg_off, W, ta, oa, tb, ob, tc, oc);
+  return hipGetLastError();
+}
+
+hipError_t launch_hist_packets(const uint32_t *src, const uint32_t *dst, const uint64_t *seg_off,
+                               const uint64_t *tile_off, uint32_t W, uint64_t max_tiles,
+                               uint32_t *hist, hipStream_t s) {
+  static uint64_t cap[64];
+  const int d = device_id();
+  if (!cap[d]) cap[d] = resident(k_hist_packets<256>, 256);
+  hipLaunchKernelGGL(k_hist_packets<256>, dim3(clamp_grid(max_tiles, cap[d])), dim3(256), 0, s,
+                     src, dst, seg_off, tile_off, W, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_hist_scan(const uint32_t *hist, uint32_t *base, uint64_t rows, hipStream_t s) {
+  if (rows == 0) return hipSuccess;
+  const uint64_t blocks = (rows + 3) / 4;  // 4 waves per block
+  hipLaunchKernelGGL(k_hist_scan, dim3((uint32_t)blocks), dim3(256), 0, s, hist, base, rows);
+  return hipGetLastError();
+}
+
+template <int B, int I, bool P>
+static hipError_t pass_impl(const PassArgs &a, uint64_t max_tiles, hipStream_t s) {
+  static uint64_t cap[64];
+  const int d = device_id();
+  if (!cap[d]) cap[d] = resident(k_pass<B, I, P>, B);
+  hipLaunchKernelGGL((k_pass<B, I, P>), dim3(clamp_grid(max_tiles, cap[d])), dim3(B), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass(const SortShape &sh, const PassArgs &a, uint64_t max_tiles, hipStream_t s) {
+  const bool P = a.src != nullptr;
+  if (sh.block == 256 && sh.items == 8) return P ? pass_impl<256, 8, true>(a, max_tiles, s) : pass_impl<256, 8, false>(a, max_tiles, s);
+  if (sh.block == 256 && sh.items == 16) return P ? pass_impl<256, 16, true>(a, max_tiles, s) : pass_impl<256, 16, false>(a, max_tiles, s);
+  if (sh.block == 512 && sh.items == 8) return P ? pass_impl<512, 8, true>(a, max_tiles, s) : pass_impl<512, 8, false>(a, max_tiles, s);
+  if (sh.block == 512 && sh.items == 16) return P ? pass_impl<512, 16, true>(a, max_tiles, s) : pass_impl<512, 16, false>(a, max_tiles, s);
+  return hipErrorInvalidValue;
+}
+
+template <int I>
+static hipError_t rle_impl(const RleArgs &a, uint64_t max_tiles, hipStream_t s) {
+  static uint64_t cap[64];
+  const int d = device_id();
+  if (!cap[d]) cap[d] = resident(k_rle<I>, 256);
+  hipLaunchKernelGGL(k_rle<I>, dim3(clamp_grid(max_tiles, cap[d])), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rle(const ScanShape &sh, const RleArgs &a, uint64_t max_tiles, hipStream_t s) {
+  if (sh.items == 4) return rle_impl<4>(a, max_tiles, s);
+  if (sh.items == 8) return rle_impl<8>(a, max_tiles, s);
+  return hipErrorInvalidValue;
+}
+
+template <int I, int M>
+static hipError_t runs_impl(const RunArgs &a, uint64_t max_tiles, hipStream_t s) {
+  static uint64_t cap[64];
+  const int d = device_id();
+  if (!cap[d]) cap[d] = resident(k_runs<I, M>, 256);
+  hipLaunchKernelGGL((k_runs<I, M>), dim3(clamp_grid(max_tiles, cap[d])), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_runs(const ScanShape &sh, int mode, const RunArgs &a, uint64_t max_tiles,
+                       hipStream_t s) {
+  if (sh.items == 4) return mode == 0 ? runs_impl<4, 0>(a, max_tiles, s) : runs_impl<4, 1>(a, max_tiles, s);
+  if (sh.items == 8) return mode == 0 ? runs_impl<8, 0>(a, max_tiles, s) : runs_impl<8, 1>(a, max_tiles, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_segmax(const uint64_t *a, const uint64_t *b, const uint64_t *head_off,
+                         uint32_t W, uint64_t max_heads, uint64_t *stats, int fa, int fb,
+                         hipStream_t s) {
+  const uint32_t g = clamp_grid((max_heads + 255) / 256, 8ull * cu_count());
+  hipLaunchKernelGGL(k_segmax, dim3(g), dim3(256), 0, s, a, b, head_off, W, stats, fa, fb);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const uint64_t *seg_off, const uint64_t *link_off,
+                           const uint64_t *row_off, const uint64_t *col_off, uint32_t W,
+                           uint64_t *stats, hipStream_t s) {
+  if (W == 0) return hipSuccess;
+  const uint32_t g = clamp_grid((W + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, seg_off, link_off, row_off, col_off, W,
+                     stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_matrix(const uint64_t *row_hval, const uint64_t *row_off,
+                                  const uint64_t *col_off, const uint64_t *nnz, uint64_t *stats,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_matrix, dim3(1), dim3(64), 0, s, row_hval, row_off, col_off, nnz,
+                     stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge(const MergeArgs &a, uint64_t max_tiles, hipStream_t s) {
+  static uint64_t cap[64];
+  const int d = device_id();
+  if (!cap[d]) cap[d] = resident(k_merge, 256);
+  hipLaunchKernelGGL(k_merge, dim3(clamp_grid(max_tiles, cap[d])), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t read_and_clear_status(int *host_status) {
+  int v = 0;
+  hipError_t e = hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_status), sizeof(int), 0,
+                                     hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return e;
+  const int zero = 0;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(g_status), &zero, sizeof(int), 0, hipMemcpyHostToDevice);
+  *host_status = v ? -5 : 0;
+  return e;
+}
+
+}  // namespace ns

@@ -1,0 +1,132 @@
+// Host-side launchers of the libns kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ns {
+
+// Byte digits of the packed key src<<32|dst: digit p covers bits [8p, 8p+8).
+constexpr int kKeyDigits = 8;
+constexpr int kColDigits = 4;  // digits 4..7 of a column item dst<<32|count
+constexpr int kBins = 256;
+
+struct SortShape {
+  int block;  // 256 or 512
+  int items;  // 8 or 16
+  int tile() const { return block * items; }
+};
+
+struct ScanShape {
+  int items;  // 4 or 8 (block is 256)
+  int tile() const { return 256 * items; }
+};
+
+constexpr int kHistTile = 256 * 32;   // packets per histogram tile
+constexpr int kMergeTile = 256 * 8;   // merged positions per merge tile
+
+// --- generic -----------------------------------------------------------------
+hipError_t launch_fill64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_fill32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+// seg[0] = 0, seg[1] = min(*n_dev, n) if n_dev else n
+hipError_t launch_seg1(uint64_t *seg, const uint64_t *n_dev, uint64_t n, hipStream_t s);
+// per-segment tile prefix for up to three tile sizes (null outputs skipped)
+hipError_t launch_tiles(const uint64_t *seg_off, uint32_t W, uint32_t ta, uint64_t *oa,
+                        uint32_t tb, uint64_t *ob, uint32_t tc, uint64_t *oc, hipStream_t s);
+
+// --- radix sort ----------------------------------------------------------------
+hipError_t launch_hist_packets(const uint32_t *src, const uint32_t *dst, const uint64_t *seg_off,
+                               const uint64_t *tile_off, uint32_t W, uint64_t max_tiles,
+                               uint32_t *hist, hipStream_t s);
+// exclusive scan of rows of 256 bins
+hipError_t launch_hist_scan(const uint32_t *hist, uint32_t *base, uint64_t rows, hipStream_t s);
+
+struct PassArgs {
+  const uint32_t *src;       // packets input (first key pass) or null
+  const uint32_t *dst;
+  const uint64_t *in;        // u64 input otherwise
+  uint64_t *out;
+  const uint64_t *seg_off;   // [W+1]
+  const uint64_t *tile_off;  // [W+1] tiles of this sort's tile size
+  uint32_t W;
+  uint32_t shift;            // digit = (key >> shift) & 255
+  const uint32_t *base;      // bucket starts of this digit: base[w*base_stride + bin]
+  uint32_t base_stride;
+  uint64_t *lb;              // look-back words of this pass [tiles][256]
+  uint64_t *lb_next;         // cleared for the next pass
+  uint32_t *ticket;
+};
+hipError_t launch_pass(const SortShape &sh, const PassArgs &a, uint64_t max_tiles, hipStream_t s);
+
+// --- run-length encoding of sorted packet keys ------------------------------------
+struct RleArgs {
+  const uint64_t *keys;
+  const uint64_t *seg_off;
+  const uint64_t *tile_off;
+  uint32_t W;
+  uint64_t *ukeys;     // nullable; may equal keys (in place)
+  uint64_t *counts;    // nullable
+  uint64_t *items;     // nullable: dst<<32 | count per link
+  uint64_t *rpos;      // nullable: packet position of each row head (+ sentinel)
+  uint64_t *rlink;     // link index of each row head (+ sentinel)
+  uint32_t *col_hist;  // nullable [W][4][256]
+  uint64_t *link_off;  // [W+1]
+  uint64_t *row_off;   // [W+1]
+  uint64_t *nnz_out;   // nullable: total links
+  uint64_t *lb;        // [tiles][2]
+  uint32_t *ticket;
+};
+hipError_t launch_rle(const ScanShape &sh, const RleArgs &a, uint64_t max_tiles, hipStream_t s);
+
+// --- run reduction over a sorted array with explicit values -----------------------
+// mode 0: rows of a matrix (group = key>>32, value = counts[p]); also emits
+//         column items and their digit histograms.
+// mode 1: columns of sorted items (group = item>>32, value = item & 0xffffffff).
+struct RunArgs {
+  const uint64_t *keys;
+  const uint64_t *counts;    // mode 0
+  const uint64_t *seg_off;
+  const uint64_t *tile_off;
+  uint32_t W;
+  uint64_t *hpos;            // head position (+ sentinel)
+  uint64_t *hval;            // exclusive value prefix at head (+ sentinel)
+  uint64_t *head_off;        // [W+1]
+  uint64_t *items;           // mode 0, nullable
+  uint32_t *col_hist;        // mode 0, nullable
+  uint64_t *lb;              // [tiles][2]
+  uint32_t *ticket;
+};
+hipError_t launch_runs(const ScanShape &sh, int mode, const RunArgs &a, uint64_t max_tiles,
+                       hipStream_t s);
+
+// per segment: stats[w][fa] = max(a[r+1]-a[r]), stats[w][fb] = max(b[r+1]-b[r])
+// over the heads r of segment w (heads [head_off[w], head_off[w+1]))
+hipError_t launch_segmax(const uint64_t *a, const uint64_t *b, const uint64_t *head_off,
+                         uint32_t W, uint64_t max_heads, uint64_t *stats, int fa, int fb,
+                         hipStream_t s);
+
+// stats[w][0..3] from segment, link, row and column offsets
+hipError_t launch_finalize(const uint64_t *seg_off, const uint64_t *link_off,
+                           const uint64_t *row_off, const uint64_t *col_off, uint32_t W,
+                           uint64_t *stats, hipStream_t s);
+// matrix stats[0..3]: valid = rows value sentinel, links = *nnz, rows, cols
+hipError_t launch_finalize_matrix(const uint64_t *row_hval, const uint64_t *row_off,
+                                  const uint64_t *col_off, const uint64_t *nnz,
+                                  uint64_t *stats, hipStream_t s);
+
+// --- union-add / subtract ---------------------------------------------------------
+struct MergeArgs {
+  const uint64_t *ka, *ca, *na;
+  const uint64_t *kb, *cb, *nb;
+  uint64_t na_max, nb_max;  // host bounds on *na, *nb
+  uint64_t *kc, *cc, *nc;
+  int sign;
+  uint64_t *lb;   // [tiles]
+  uint32_t *ticket;
+};
+hipError_t launch_merge(const MergeArgs &a, uint64_t max_tiles, hipStream_t s);
+
+// device error word
+hipError_t read_and_clear_status(int *host_status);
+
+}  // namespace ns

@@ -1,0 +1,88 @@
+"""libns.so loads on a host without a GPU and exports every symbol of include/ns.h."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2510_14050_amd import ns
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "ns.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(ns_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ns.LIB_PATH):
+        pytest.skip("libns.so not built")
+    return ns.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("ns_build_matrix", "ns_accumulate", "ns_stats", "ns_batch_stats",
+              "ns_workspace_size", "ns_device_status", "ns_release_graphs", "ns_error_string"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert set(declared_functions()) == set(ns.EXPORTS)
+
+
+def test_host_only_calls(lib):
+    assert ns.version().startswith("libns")
+    assert lib.ns_error_string(-2) == b"output capacity below the a-priori bound"
+    small = ns.workspace_size(0, 1)
+    big = ns.workspace_size(1 << 20, 64)
+    assert 0 < small < big
+    # workspace grows about linearly in packets (sort buffers + head arrays)
+    assert ns.workspace_size(1 << 22, 1) > 4 * ns.workspace_size(1 << 20, 1) * 0.9
+    bad = ctypes.c_uint64()
+    assert lib.ns_workspace_size(10, 1, None) == -1
+    assert lib.ns_workspace_size(10, 1, ctypes.byref(bad)) == 0
+
+
+def test_host_argument_errors(lib):
+    """Errors found on the host return before anything touches a device."""
+    m = ns.MatrixView(0, 0, 0, 0, 0)
+    assert lib.ns_build_matrix(None, None, 0, None, None, 0, None) == -1
+    assert lib.ns_build_matrix(None, None, 5, ctypes.byref(m), None, 0, None) == -1
+    fake = ns.MatrixView(256, 512, 768, 10, 10)
+    # capacity below n
+    assert lib.ns_build_matrix(ctypes.c_void_p(256), ctypes.c_void_p(256), 11,
+                               ctypes.byref(fake), ctypes.c_void_p(256), 1 << 40, None) == -2
+    # n beyond 2^32 - 1
+    assert lib.ns_build_matrix(ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 32,
+                               ctypes.byref(fake), ctypes.c_void_p(256), 1 << 40, None) == -6
+    # misaligned / short workspace
+    assert lib.ns_build_matrix(ctypes.c_void_p(256), ctypes.c_void_p(256), 4, ctypes.byref(fake),
+                               ctypes.c_void_p(100), 1 << 40, None) == -3
+    assert lib.ns_build_matrix(ctypes.c_void_p(256), ctypes.c_void_p(256), 4, ctypes.byref(fake),
+                               ctypes.c_void_p(256), 16, None) == -3
+    # accumulate: bad sign, aliasing, capacity, host-visible underflow
+    a = ns.MatrixView(1024, 2048, 3072, 100, 100)
+    b = ns.MatrixView(4096, 5120, 6144, 50, 50)
+    c = ns.MatrixView(7168, 8192, 9216, 150, 0)
+    ws = ctypes.c_void_p(1 << 20)
+    assert lib.ns_accumulate(ctypes.byref(a), ctypes.byref(b), 0, ctypes.byref(c), ws, 1 << 40, None) == -1
+    assert lib.ns_accumulate(ctypes.byref(a), ctypes.byref(b), 1, ctypes.byref(a), ws, 1 << 40, None) == -1
+    small = ns.MatrixView(7168, 8192, 9216, 149, 0)
+    assert lib.ns_accumulate(ctypes.byref(a), ctypes.byref(b), 1, ctypes.byref(small), ws, 1 << 40, None) == -2
+    assert lib.ns_accumulate(ctypes.byref(b), ctypes.byref(a), -1, ctypes.byref(c), ws, 1 << 40, None) == -5
+    # stats of a matrix holding 2^32 packets or more is out of range
+    huge = ns.MatrixView(1024, 2048, 3072, 100, 1 << 32)
+    assert lib.ns_stats(ctypes.byref(huge), ctypes.c_void_p(256), ws, 1 << 40, None) == -6
+    # batch: bad tuning, capacity
+    t = ns.tuning(sort_block=128)
+    off = ctypes.c_void_p(256)
+    assert lib.ns_batch_stats(off, off, off, 1, 10, off, None, None, None, ctypes.byref(t), ws,
+                              1 << 40, None) == -1
+    aggm = ns.MatrixView(1024, 2048, 3072, 9, 0)
+    assert lib.ns_batch_stats(off, off, off, 1, 10, off, ctypes.byref(aggm), None, None, None, ws,
+                              1 << 40, None) == -2
