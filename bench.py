@@ -39,6 +39,13 @@ def parse():
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="target CPU time of the oracle baseline sample")
+    p.add_argument("--serve-arrivals", type=int, default=3072,
+                   help="serving leg: arrivals (the first --serve-warm are warm-up); 0 = skip")
+    p.add_argument("--serve-warm", type=int, default=1024)
+    p.add_argument("--serve-rate", type=float, default=2000.0)
+    p.add_argument("--copy-calibration-mib", type=int, default=0,
+                   help="first run a plain device copy of this many MiB (3 times), whose "
+                        "memory counters calibrate the profiler's byte counts")
     return p.parse_args()
 
 
@@ -62,6 +69,17 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     ns.load()
+
+    if args.copy_calibration_mib:
+        n64 = args.copy_calibration_mib * (1 << 20) // 8
+        a = torch.ones(n64, dtype=torch.int64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {args.copy_calibration_mib} MiB "
+            f"(read {args.copy_calibration_mib} MiB + write {args.copy_calibration_mib} MiB each)")
+        del a, b
 
     wl = synth.WORKLOADS[args.workload]()
     W, N = wl.num_windows, wl.total_packets
@@ -182,6 +200,10 @@ def main():
             bit_exact = bit_exact and bool(np.array_equal(got_agg, agg_want))
         log(f"oracle: {cpu_rate:.4e} packets/s on {sampled_w} windows; bit-exact {bit_exact}")
 
+    serving = None
+    if args.serve_arrivals > 0:
+        serving = serve_leg(args, dev)
+
     line = {
         "metric": "packets/sec (8 stats, bit-exact) batched vs plain; p50/p99 window latency",
         "value": value,
@@ -209,8 +231,57 @@ def main():
         "batched_vs_plain": round(value / plain["value"], 2) if plain else None,
         "bit_exact": bit_exact,
         "kernels_ms": breakdown,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
+
+
+def serve_leg(args, dev):
+    """Serving workload: windows of 2^10..2^17 packets (Zipf 1.2, pool 2^22),
+    Poisson arrivals, rolling aggregate over the last 1024 windows, stats per
+    arrival; p50/p99 over the arrivals after the warm-up."""
+    import numpy as np
+    import torch
+
+    from paper_2510_14050_amd import serve, synth
+    n = args.serve_arrivals
+    wl = synth.serving(num=n, rate=args.serve_rate)
+    log(f"serving: generating {n} windows ({wl.total_packets} packets)")
+    wins = []
+    for w in range(n):
+        s_t, d_t = wl.window(w, device=dev)
+        wins.append((synth.as_u32(s_t), synth.as_u32(d_t)))
+    torch.cuda.synchronize()
+    srv = serve.Server(ring=1024, max_window=1 << 17, max_batch=16, budget_bytes=4 << 30,
+                       device=dev)
+    # warm the library (first launches) off the clock
+    srv.run(wins[:8])
+    rep = srv.run(wins, arrivals_s=wl.arrivals[:n] - wl.arrivals[0])
+    lat = rep.latencies_ms()[args.serve_warm:]
+    measured = rep.results[args.serve_warm:]
+    pk = sum(r.packets for r in measured)
+    span = (measured[-1].t_done - measured[0].t_arrival) if measured else 0.0
+    # spot-check a few rolling snapshots against the oracle
+    import oracle
+    checks = []
+    for k in (args.serve_warm, n - 1):
+        lo = max(0, k - 1023)
+        want = oracle.stats(np.concatenate([wins[j][0] for j in range(lo, k + 1)]),
+                            np.concatenate([wins[j][1] for j in range(lo, k + 1)]))
+        checks.append(bool(np.array_equal(rep.results[k].rolling_stats, want)))
+    out = {
+        "workload": wl.name, "arrivals": n, "warmup_arrivals": args.serve_warm,
+        "offered_windows_per_s": args.serve_rate, "ring": 1024,
+        "p50_ms": round(float(np.percentile(lat, 50)), 3) if lat.size else None,
+        "p99_ms": round(float(np.percentile(lat, 99)), 3) if lat.size else None,
+        "mean_ms": round(float(lat.mean()), 3) if lat.size else None,
+        "packets_per_s": pk / span if span else None,
+        "mean_batch": round(float(np.mean(rep.batches)), 2),
+        "max_batch": int(max(rep.batches)), "max_in_flight": rep.max_in_flight,
+        "rolling_spot_checks_bit_exact": checks,
+    }
+    log("serving:", json.dumps(out))
+    return out
 
 
 if __name__ == "__main__":

@@ -90,14 +90,16 @@ typedef struct {
   uint32_t scan_items;
 } ns_tuning_t;
 
-/* Per-window matrices of a batch, stored back to back (batched COO).
- * Window w owns entries [offsets[w], offsets[w+1]) of keys/counts; offsets
- * has num_windows+1 device entries written by the library; capacity (host)
- * must be >= the batch's total packets. */
+/* Per-window matrices of a batch, laid out by packet offset: window w's
+ * sorted COO occupies keys/counts[offsets[w] .. offsets[w] + nnz[w]) where
+ * offsets are the batch's packet offsets (so a caller that knows them can
+ * address any window's matrix without reading the device), and nnz is a device
+ * array of num_windows entries written by the library. capacity (host) must be
+ * >= the batch's total packets. */
 typedef struct {
   uint64_t *keys;
   uint64_t *counts;
-  uint64_t *offsets;
+  uint64_t *nnz;
   uint64_t capacity;
 } ns_batch_matrices_t;
 

@@ -29,7 +29,7 @@ uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 // Workspace carve-up for at most N packets / entries and W windows.
 struct Layout {
   uint64_t tickets, seg, t_sort, t_hist, t_rle, t_csort, t_run;
-  uint64_t link_off, row_off, col_off;
+  uint64_t link_off, row_off, col_off, seg_base;
   uint64_t hist, base, chist, cbase;
   uint64_t lb0, lb1, lbs;
   uint64_t KA, KB, HA, HB;
@@ -55,6 +55,7 @@ Layout plan(uint64_t N, uint32_t W) {
   L.link_off = take(W1 * 8);
   L.row_off = take(W1 * 8);
   L.col_off = take(W1 * 8);
+  L.seg_base = take(W1 * 8);
   L.hist = take(Wd * kKeyDigits * kBins * 4);
   L.base = take(Wd * kKeyDigits * kBins * 4);
   L.chist = take(Wd * kColDigits * kBins * 4);
@@ -220,7 +221,9 @@ struct PacketOut {
   uint64_t *ukeys;         // matrix keys (may be the in-place sorted buffer) or null
   uint64_t *counts;        // matrix counts or null
   uint64_t *nnz;           // total links (device scalar) or null
-  uint64_t *link_off;      // [W+1] output offsets (or null: workspace)
+  uint64_t *win_keys;      // positional per-window matrices (or null)
+  uint64_t *win_counts;
+  uint64_t *win_nnz;       // [W]
   uint64_t *sort_a;        // sort ping-pong buffers (capacity >= N each); the sorted
   uint64_t *sort_b;        // keys end in sort_b
 };
@@ -233,7 +236,7 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
            *t_rle = ws.at<uint64_t>(L.t_rle);
   uint32_t *hist = ws.at<uint32_t>(L.hist), *base = ws.at<uint32_t>(L.base);
   uint32_t *chist = ws.at<uint32_t>(L.chist);
-  uint64_t *link_off = o.link_off ? o.link_off : ws.at<uint64_t>(L.link_off);
+  uint64_t *link_off = ws.at<uint64_t>(L.link_off);
   uint64_t *row_off = ws.at<uint64_t>(L.row_off);
   uint64_t *lb[2] = {ws.at<uint64_t>(L.lb0), ws.at<uint64_t>(L.lb1)};
   const uint64_t sort_tiles = N / sh.sort.tile() + W + 1;
@@ -250,6 +253,10 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
   HIP_TRY(launch_fill64(link_off, (uint64_t)W + 1, 0, s));
   HIP_TRY(launch_fill64(row_off, (uint64_t)W + 1, 0, s));
   if (o.nnz) HIP_TRY(launch_fill64(o.nnz, 1, 0, s));
+  if (o.win_keys) {
+    HIP_TRY(launch_fill64(o.win_nnz, W, 0, s));
+    HIP_TRY(launch_fill64(ws.at<uint64_t>(L.seg_base), W, 0, s));
+  }
   HIP_TRY(launch_tiles(seg_off, W, sh.sort.tile(), t_sort, kHistTile, t_hist, sh.scan.tile(),
                        t_rle, s));
   HIP_TRY(timed(K_HIST, s, [&] { return launch_hist_packets(src, dst, seg_off, t_hist, W, hist_tiles, hist, s); }));
@@ -297,6 +304,10 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
   r.ukeys = o.ukeys;
   r.counts = o.counts;
   r.items = items;
+  r.win_keys = o.win_keys;
+  r.win_counts = o.win_counts;
+  r.win_nnz = o.win_nnz;
+  r.seg_base = ws.at<uint64_t>(L.seg_base);
   r.rpos = rpos;
   r.rlink = rlink;
   r.col_hist = want_stats ? chist : nullptr;
@@ -404,9 +415,9 @@ int enqueue_batch(const BatchArgs &b, Ws &ws, hipStream_t s) {
     o.sort_a = ws.at<uint64_t>(ws.L.KA);
     o.sort_b = ws.at<uint64_t>(ws.L.KB);
     if (b.win) {
-      o.ukeys = b.win->keys;
-      o.counts = b.win->counts;
-      o.link_off = b.win->offsets;
+      o.win_keys = b.win->keys;
+      o.win_counts = b.win->counts;
+      o.win_nnz = b.win->nnz;
     }
     int rc = enqueue_packets(ws, b.sh, b.src, b.dst, b.offsets, b.W, b.N, o, s);
     if (rc) return rc;
@@ -441,7 +452,7 @@ int batch_checks(const uint32_t *src, const uint32_t *dst, const uint64_t *offse
     if (agg->capacity < N) return NS_ERR_CAPACITY;
   }
   if (win) {
-    if (!win->keys || !win->counts || !win->offsets) return NS_ERR_INVALID_ARG;
+    if (!win->keys || !win->counts || !win->nnz) return NS_ERR_INVALID_ARG;
     if (win->capacity < N) return NS_ERR_CAPACITY;
   }
   b->sh = Shapes{};
@@ -469,7 +480,7 @@ std::string batch_key(int dev, const BatchArgs &b, void *ws, uint64_t ws_bytes) 
            b.agg ? (void *)b.agg->counts : nullptr, b.agg ? (void *)b.agg->nnz : nullptr,
            (unsigned long long)(b.agg ? b.agg->capacity : 0), (void *)b.agg_stats,
            b.win ? (void *)b.win->keys : nullptr, b.win ? (void *)b.win->counts : nullptr,
-           b.win ? (void *)b.win->offsets : nullptr, (void *)nullptr,
+           b.win ? (void *)b.win->nnz : nullptr, (void *)nullptr,
            (unsigned long long)(b.win ? b.win->capacity : 0), b.sh.sort.block, b.sh.sort.items,
            b.sh.scan.items, ws, (unsigned long long)ws_bytes);
   return std::string(buf);

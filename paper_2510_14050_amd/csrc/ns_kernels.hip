@@ -297,7 +297,7 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
   __shared__ uint32_t s_rlr[TILE];
   __shared__ uint32_t s_ch[kColDigits * kBins];
   __shared__ uint64_t s_tmp[BLOCK / kWave];
-  __shared__ uint64_t s_L0, s_R0, s_trail;
+  __shared__ uint64_t s_L0, s_R0, s_trail, s_base;
   __shared__ uint32_t s_tile;
 
   const int tid = threadIdx.x;
@@ -375,6 +375,22 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
     }
     __syncthreads();
     const uint64_t L0 = s_L0, R0 = s_R0, trail = s_trail;
+    // positional per-segment output: global link index at this segment's start,
+    // published by the segment's first tile (an earlier ticket, so it arrives)
+    if (a.win_keys && tid == 0) {
+      if (t == first) {
+        lb_store(a.seg_base + w, kLbInc | L0);
+        s_base = L0;
+      } else {
+        uint64_t v = lb_load(a.seg_base + w);
+        while ((v >> 62) == 0) {
+          __builtin_amdgcn_s_sleep(1);
+          v = lb_load(a.seg_base + w);
+        }
+        s_base = v & kLbVal;
+      }
+      if (t + 1 == (uint32_t)a.tile_off[w + 1]) a.win_nnz[w] = L0 + TL - s_base;
+    }
     if (tid == 0) {
       if (t == first) {
         a.link_off[w] = L0;
@@ -397,6 +413,8 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
         if (a.nnz_out) *a.nnz_out = Le;
       }
     }
+    if (a.win_keys) __syncthreads();  // s_base
+    const uint64_t wpos = a.win_keys ? seg_lo + L0 - s_base : 0;
     for (uint32_t r = tid; r < TL; r += BLOCK) {
       const uint32_t p = s_hpos[r];
       const uint64_t K = s_k[1 + p];
@@ -405,6 +423,10 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
       const uint64_t L = L0 + r;
       if (a.ukeys) a.ukeys[L] = K;
       if (a.counts) a.counts[L] = cnt;
+      if (a.win_keys) {
+        a.win_keys[wpos + r] = K;
+        a.win_counts[wpos + r] = cnt;
+      }
       if (a.items) a.items[L] = (K << 32) | cnt;
       if (a.col_hist) {
         const uint32_t d = (uint32_t)K;

@@ -67,6 +67,10 @@ struct RleArgs {
   uint64_t *ukeys;     // nullable; may equal keys (in place)
   uint64_t *counts;    // nullable
   uint64_t *items;     // nullable: dst<<32 | count per link
+  uint64_t *win_keys;  // nullable: positional per-segment matrices (segment w's links
+  uint64_t *win_counts;//   start at seg_off[w]); then seg_base and win_nnz are used
+  uint64_t *win_nnz;   // [W] links per segment
+  uint64_t *seg_base;  // [W] flagged words: global link index at each segment start
   uint64_t *rpos;      // nullable: packet position of each row head (+ sentinel)
   uint64_t *rlink;     // link index of each row head (+ sentinel)
   uint32_t *col_hist;  // nullable [W][4][256]

@@ -53,7 +53,7 @@ class Tuning(ctypes.Structure):
 
 class BatchMatricesView(ctypes.Structure):
     _fields_ = [("keys", ctypes.c_void_p), ("counts", ctypes.c_void_p),
-                ("offsets", ctypes.c_void_p), ("capacity", ctypes.c_uint64)]
+                ("nnz", ctypes.c_void_p), ("capacity", ctypes.c_uint64)]
 
 
 EXPORTS = ("ns_workspace_size", "ns_build_matrix", "ns_accumulate", "ns_stats",
@@ -164,6 +164,14 @@ class Matrix:
         self.nnz_t = torch.zeros(1, dtype=torch.int64, device=device)
         self.packets = 0
 
+    @classmethod
+    def wrap(cls, keys, counts, nnz_t, capacity: int, packets: int) -> "Matrix":
+        """A Matrix over existing device tensors (no allocation)."""
+        m = cls.__new__(cls)
+        m.keys, m.counts, m.nnz_t = keys, counts, nnz_t
+        m.capacity, m.packets = int(capacity), int(packets)
+        return m
+
     def view(self) -> MatrixView:
         return MatrixView(self.keys.data_ptr(), self.counts.data_ptr(), self.nnz_t.data_ptr(),
                           self.capacity, self.packets)
@@ -217,18 +225,26 @@ def stats(m: Matrix, out, ws: Workspace, stream=None):
 
 
 class BatchMatrices:
-    """Per-window matrices of a batch, back to back (batched COO)."""
+    """Per-window matrices of a batch, laid out by packet offset: window w's
+    entries start at the window's first packet position; nnz[w] on the device."""
 
-    def __init__(self, capacity: int, num_windows: int, device="cuda"):
+    def __init__(self, capacity: int, num_windows: int, device="cuda", keys=None, counts=None):
         torch = _torch()
         self.capacity = int(capacity)
-        self.keys = torch.empty(max(capacity, 1), dtype=torch.int64, device=device)
-        self.counts = torch.empty(max(capacity, 1), dtype=torch.int64, device=device)
-        self.offsets = torch.zeros(num_windows + 1, dtype=torch.int64, device=device)
+        n = max(self.capacity, 1)
+        self.keys = keys if keys is not None else torch.empty(n, dtype=torch.int64, device=device)
+        self.counts = counts if counts is not None else torch.empty(n, dtype=torch.int64,
+                                                                     device=device)
+        self.nnz = torch.zeros(max(num_windows, 1), dtype=torch.int64, device=device)
 
     def view(self) -> BatchMatricesView:
         return BatchMatricesView(self.keys.data_ptr(), self.counts.data_ptr(),
-                                 self.offsets.data_ptr(), self.capacity)
+                                 self.nnz.data_ptr(), self.capacity)
+
+    def window(self, w: int, start: int, n: int) -> "Matrix":
+        """Matrix view of window w, whose packets were [start, start + n) of the batch."""
+        return Matrix.wrap(self.keys[start:start + max(n, 1)],
+                           self.counts[start:start + max(n, 1)], self.nnz[w:w + 1], n, n)
 
 
 def tuning(sort_block=0, sort_items=0, digit_bits=0, scan_items=0) -> Tuning:

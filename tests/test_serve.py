@@ -1,0 +1,125 @@
+"""Serving loop: arena bookkeeping (CPU) and end-to-end results (GPU).
+
+Every arrival's window quantities and rolling-aggregate quantities must equal
+the oracle's, whatever the micro-batching and timing ("alone" = one window at
+a time with nothing else in flight; "in the mix" = Poisson arrivals with
+continuous batching and overlapping device work).
+"""
+import sys
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import oracle
+from paper_2510_14050_amd import synth
+from paper_2510_14050_amd.serve import RingArena
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@settings(max_examples=200, deadline=None)
+@given(st.integers(16, 400), st.lists(st.tuples(st.booleans(), st.integers(1, 120)),
+                                      max_size=200))
+def test_ring_arena_fifo(cap, ops):
+    """Live regions never overlap, stay in [0, cap), and frees are FIFO."""
+    ar = RingArena(cap)
+    live = []
+    for is_alloc, n in ops:
+        if is_alloc:
+            can = ar.can_alloc(n)
+            s = ar.alloc(n)
+            assert (s is not None) == can
+            if s is not None:
+                assert 0 <= s and s + n <= cap
+                for a, b in live:
+                    assert s + n <= a or b <= s, "overlap"
+                live.append((s, s + n))
+        elif live:
+            ar.free_oldest()
+            live.pop(0)
+    # with nothing live, the whole capacity is available
+    while live:
+        ar.free_oldest()
+        live.pop(0)
+    assert ar.can_alloc(cap)
+
+
+def test_ring_arena_wraps():
+    ar = RingArena(10)
+    assert ar.alloc(4) == 0
+    assert ar.alloc(4) == 4
+    assert ar.alloc(4) is None      # only 2 left at the end, none at the front
+    ar.free_oldest()
+    assert ar.alloc(3) == 0         # wraps to the freed front
+    assert ar.alloc(2) is None
+    ar.free_oldest()
+    assert ar.alloc(5) == 3
+
+
+def small_windows(n_windows, seed=5, lo=8, hi=12):
+    wl = synth.Workload("serve_t", seed, 1 << 12, 1.2, 1.2,
+                        synth.log_uniform_sizes(seed, n_windows, lo, hi))
+    return [wl.window(w) for w in range(n_windows)]
+
+
+def rolling_want(windows, ring):
+    out = []
+    for k in range(len(windows)):
+        lo = max(0, k - ring + 1)
+        s = np.concatenate([windows[j][0] for j in range(lo, k + 1)])
+        d = np.concatenate([windows[j][1] for j in range(lo, k + 1)])
+        out.append(oracle.stats(s, d))
+    return out
+
+
+@pytest.mark.gpu
+def test_serving_alone_and_in_the_mix():
+    import torch
+    from paper_2510_14050_amd.serve import Server
+    ring, n = 6, 40
+    wins = small_windows(n)
+    want_roll = rolling_want(wins, ring)
+    want_win = [oracle.stats(s, d) for s, d in wins]
+    srv = Server(ring=ring, max_window=1 << 12, max_batch=4, budget_bytes=64 << 20,
+                 timing=True)
+    say("serve alone (max_batch 1, serial)")
+    alone = Server(ring=ring, max_window=1 << 12, max_batch=1, budget_bytes=64 << 20)
+    rep_alone = alone.run(wins)
+    say("serve in the mix (all arrive at once)")
+    rep_burst = srv.run(wins)
+    say("serve in the mix (Poisson arrivals)")
+    arr = synth.poisson_arrivals(9, n, 4000.0)
+    rep_poisson = srv.run(wins, arrivals_s=arr)
+    torch.cuda.synchronize()
+    for rep in (rep_alone, rep_burst, rep_poisson):
+        for k, r in enumerate(rep.results):
+            assert r.seq == k
+            assert r.window_stats.tolist() == want_win[k].tolist(), k
+            assert r.rolling_stats.tolist() == want_roll[k].tolist(), k
+    # continuous batching really grouped arrivals and overlapped device work
+    assert max(rep_burst.batches) > 1
+    assert rep_burst.max_in_flight >= 2
+    assert rep_burst.device_overlap() >= 1 or max(rep_burst.batches) > 1
+    s = rep_poisson.summary()
+    assert s["p50_ms"] is not None and s["p99_ms"] >= s["p50_ms"]
+
+
+@pytest.mark.gpu
+def test_serving_memory_budget_gates_admission():
+    """A budget that only fits the ring plus two micro-batches still serves
+    everything correctly (admission waits for memory)."""
+    from paper_2510_14050_amd.serve import Server
+    ring, n = 4, 30
+    wins = small_windows(n, seed=8, lo=10, hi=12)
+    want_roll = rolling_want(wins, ring)
+    mw = 1 << 12
+    budget = 16 * (ring + 2 * 2) * mw + 8 * 2 * mw
+    srv = Server(ring=ring, max_window=mw, max_batch=2, budget_bytes=budget)
+    rep = srv.run(wins)
+    for k, r in enumerate(rep.results):
+        assert r.rolling_stats.tolist() == want_roll[k].tolist(), k
+    with pytest.raises(ValueError):
+        Server(ring=ring, max_window=mw, max_batch=2, budget_bytes=budget - 1)
