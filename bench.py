@@ -63,7 +63,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2510_14050_amd import ns, synth
+    from paper_2510_14050_amd import ns, synth, tune
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
@@ -93,8 +93,14 @@ def main():
     agg_stats = torch.zeros(8, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
 
+    shape = tune.lookup(N, W)  # autotuned launch shape for this size class, if cached
+    sort_block = shape.sort_block if shape else 256
+    sort_items = shape.sort_items if shape else 16
+    log(f"launch shape: radix {sort_block}x{sort_items}, scan 256x"
+        f"{shape.scan_items if shape else 8} ({'autotuned' if shape else 'default'})")
+
     def step():
-        ns.batch_stats(src_t, dst_t, off_t, out, ws, agg=agg, agg_stats=agg_stats)
+        ns.batch_stats(src_t, dst_t, off_t, out, ws, agg=agg, agg_stats=agg_stats, tune=shape)
 
     for _ in range(args.warmup):
         step()
@@ -114,7 +120,8 @@ def main():
     # --- per-kernel durations from HIP events (eager replay of the same step) ---
     ns.timing_reset()
     ns.timing_enable(True)
-    ns.batch_stats(src_t, dst_t, off_t, out, ws, agg=agg, agg_stats=agg_stats, graph=False)
+    ns.batch_stats(src_t, dst_t, off_t, out, ws, agg=agg, agg_stats=agg_stats, tune=shape,
+                   graph=False)
     torch.cuda.synchronize()
     kt = ns.timing_read()
     ns.timing_enable(False)
@@ -223,7 +230,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": None,
-                     "kernel": "ns::k_pass<256,16,false> (radix pass, key and column)",
+                     "kernel": f"ns::k_pass<{sort_block}, {sort_items}, false> "
+                               "(radix pass: key passes 2-8 and column passes)",
                      "avg_launch_ms": round(avg_launch_ms, 5), "launches": pass_n,
                      "algorithmic_bytes_per_launch": round(pass_bytes / max(pass_n, 1))},
         "cpu_baseline": cpu,

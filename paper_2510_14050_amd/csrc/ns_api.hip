@@ -109,18 +109,16 @@ bool capturing(hipStream_t s) {
   return st != hipStreamCaptureStatusNone;
 }
 
-// Runs `launch` (returning hipError_t), bracketed by events when timing is on.
+// Runs `launch` (returning hipError_t) with kernel timing of the given kind
+// switched on for this thread when profiling is enabled and the stream is not
+// being captured: each kernel it launches records its own start/stop events.
 template <typename F>
-hipError_t timed(int kind, hipStream_t s, F launch) {
+hipError_t timed(int kind, hipStream_t s, F launch, int = 1) {
   Profiler &p = prof();
   if (!p.on || capturing(s)) return launch();
-  Profiler::Mark m{kind, nullptr, nullptr};
-  if (hipEventCreate(&m.a) != hipSuccess || hipEventCreate(&m.b) != hipSuccess) return launch();
-  hipError_t e = hipEventRecord(m.a, s);
-  if (e == hipSuccess) e = launch();
-  if (e == hipSuccess) e = hipEventRecord(m.b, s);
-  std::lock_guard<std::mutex> lock(p.mu);
-  p.marks.push_back(m);
+  tl_timing_kind = kind;
+  const hipError_t e = launch();
+  tl_timing_kind = -1;
   return e;
 }
 
@@ -174,21 +172,25 @@ int enqueue_columns(Ws &ws, const Shapes &sh, uint64_t *items, uint64_t *tmp,
   const uint64_t sort_tiles = max_items / sh.sort.tile() + W + 1;
   uint64_t *lb[2] = {ws.at<uint64_t>(L.lb0), ws.at<uint64_t>(L.lb1)};
   uint64_t *buf[2] = {items, tmp};
-  for (int q = 0; q < kColDigits; ++q) {
-    PassArgs a{};
-    a.in = buf[q & 1];
-    a.out = buf[(q + 1) & 1];
-    a.seg_off = link_off;
-    a.tile_off = t_csort;
-    a.W = W;
-    a.shift = 32 + 8 * q;
-    a.base = cbase + q * kBins;
-    a.base_stride = kColDigits * kBins;
-    a.lb = lb[q & 1];
-    a.lb_next = lb[(q + 1) & 1];
-    a.ticket = ws.ticket();
-    HIP_TRY(timed(K_CPASS, s, [&] { return launch_pass(sh.sort, a, sort_tiles, s); }));
-  }
+  HIP_TRY(timed(K_CPASS, s, [&] {
+    for (int q = 0; q < kColDigits; ++q) {
+      PassArgs a{};
+      a.in = buf[q & 1];
+      a.out = buf[(q + 1) & 1];
+      a.seg_off = link_off;
+      a.tile_off = t_csort;
+      a.W = W;
+      a.shift = 32 + 8 * q;
+      a.base = cbase + q * kBins;
+      a.base_stride = kColDigits * kBins;
+      a.lb = lb[q & 1];
+      a.lb_next = lb[(q + 1) & 1];
+      a.ticket = ws.ticket();
+      const hipError_t e = launch_pass(sh.sort, a, sort_tiles, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }, kColDigits));
   // 4 passes: sorted items are back in `items`
   uint64_t *lbs = ws.at<uint64_t>(L.lbs);
   uint64_t *hpos = ws.at<uint64_t>(L.HA), *hval = ws.at<uint64_t>(L.HB);
@@ -263,7 +265,7 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
   HIP_TRY(timed(K_HSCAN, s, [&] { return launch_hist_scan(hist, base, (uint64_t)W * kKeyDigits, s); }));
   // 8 stable byte passes, least significant first; pass p writes buf[p & 1]
   uint64_t *buf[2] = {o.sort_a, o.sort_b};
-  for (int p = 0; p < kKeyDigits; ++p) {
+  auto pass = [&](int p) {
     PassArgs a{};
     if (p == 0) {
       a.src = src;
@@ -281,9 +283,16 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
     a.lb = lb[p & 1];
     a.lb_next = lb[(p + 1) & 1];
     a.ticket = ws.ticket();
-    HIP_TRY(timed(p == 0 ? K_PASS0 : K_PASS, s,
-                  [&] { return launch_pass(sh.sort, a, sort_tiles, s); }));
-  }
+    return launch_pass(sh.sort, a, sort_tiles, s);
+  };
+  HIP_TRY(timed(K_PASS0, s, [&] { return pass(0); }));
+  HIP_TRY(timed(K_PASS, s, [&] {
+    for (int p = 1; p < kKeyDigits; ++p) {
+      const hipError_t e = pass(p);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }, kKeyDigits - 1));
   uint64_t *sorted = buf[(kKeyDigits - 1) & 1];  // == sort_b
   // run-length encoding (+ rows and column items when statistics are wanted)
   uint64_t *lbs = ws.at<uint64_t>(L.lbs);
@@ -378,6 +387,14 @@ int enqueue_matrix_stats(Ws &ws, const Shapes &sh, const ns_matrix_t *m, uint64_
 }
 
 }  // namespace
+
+namespace ns {
+void record_timing(int kind, hipEvent_t start, hipEvent_t stop) {
+  Profiler &p = prof();
+  std::lock_guard<std::mutex> lock(p.mu);
+  p.marks.push_back(Profiler::Mark{kind, start, stop});
+}
+}  // namespace ns
 
 // ===========================================================================
 // graph cache for the batched path

@@ -51,6 +51,11 @@ __device__ __forceinline__ uint64_t lb_walk(const uint64_t *lb, uint32_t stride,
 // ---------------------------------------------------------------------------
 // wave / block helpers
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 
 // number of set bits of m in lanes below this one
@@ -106,6 +111,66 @@ __device__ __forceinline__ uint32_t find_owner(const uint64_t *off, uint32_t W, 
     if (off[mid] <= t) lo = mid; else hi = mid;
   }
   return lo;
+}
+
+// Same result as lb_walk, with up to four predecessor words in flight per
+// round trip (each thread issues the loads of tiles j, j-1, j-2, j-3 together).
+__device__ __forceinline__ uint64_t lb_walk4(const uint64_t *lb, uint32_t stride, uint32_t chan,
+                                             uint32_t t, uint32_t first) {
+  uint64_t excl = 0;
+  int64_t j = (int64_t)t - 1;
+  while (j >= (int64_t)first) {
+    uint64_t v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      v[q] = (j - q >= (int64_t)first) ? lb_load(lb + (uint64_t)(j - q) * stride + chan) : 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (j - q < (int64_t)first) return excl;
+      const uint64_t *p = lb + (uint64_t)(j - q) * stride + chan;
+      while ((v[q] >> 62) == 0) {
+        __builtin_amdgcn_s_sleep(1);
+        v[q] = lb_load(p);
+      }
+      excl += v[q] & kLbVal;
+      if ((v[q] >> 62) == 2) return excl;
+    }
+    j -= 4;
+  }
+  return excl;
+}
+
+// Wave-parallel look-back over a single chain (all tiles 0..t-1): the 64 lanes
+// of the calling wave inspect 64 predecessors at once, wait until every tile
+// up to the nearest inclusive prefix has published, and add them up. One round
+// trip covers 64 tiles instead of one. Every lane returns the same value; the
+// whole wave must call it.
+__device__ __forceinline__ uint64_t lb_walk_wave(const uint64_t *lb, uint32_t stride,
+                                                 uint32_t chan, uint32_t t) {
+  const int lane = threadIdx.x & 63;
+  uint64_t excl = 0;
+  int64_t top = (int64_t)t - 1;
+  while (top >= 0) {
+    const int64_t j = top - lane;
+    const uint64_t *p = lb + (j >= 0 ? (uint64_t)j * stride + chan : 0);
+    uint64_t v = (j >= 0) ? lb_load(p) : (2ull << 62);  // before tile 0: inclusive 0
+    int first_inc;
+    for (;;) {
+      const uint64_t inc = __ballot((v >> 62) == 2);
+      const uint64_t empty = __ballot((v >> 62) == 0);
+      first_inc = inc ? __ffsll((long long)inc) - 1 : 64;
+      const uint64_t need = first_inc >= 63 ? ~0ull : ((2ull << first_inc) - 1);
+      if ((empty & need) == 0) break;
+      if ((v >> 62) == 0) {
+        __builtin_amdgcn_s_sleep(1);
+        v = lb_load(p);
+      }
+    }
+    excl += wave_sum(lane <= first_inc ? (v & kLbVal) : 0);
+    if (first_inc < 64) break;
+    top -= 64;
+  }
+  return excl;
 }
 
 __device__ __forceinline__ uint64_t pack_key(uint32_t s, uint32_t d) {

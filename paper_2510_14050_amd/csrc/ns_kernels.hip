@@ -7,6 +7,8 @@
 // ticket, and the tile count is read from device memory. That makes the whole
 // sequence capturable in one HIP graph and keeps the look-back waits safe
 // (a waited-on tile always belongs to a running workgroup).
+#include <hip/hip_ext.h>
+
 #include "ns_device.h"
 #include "ns_launch.h"
 
@@ -90,16 +92,28 @@ __global__ __launch_bounds__(BLOCK) void k_hist_packets(const uint32_t *__restri
     const uint32_t w = find_owner(tile_off, W, t);
     const uint64_t start = seg_off[w] + (t - tile_off[w]) * (uint64_t)kHistTile;
     const uint64_t end = min(start + (uint64_t)kHistTile, seg_off[w + 1]);
-    for (uint64_t i = start + threadIdx.x; i < end; i += BLOCK) {
-      const uint32_t d = dst[i], s = src[i];
-      atomicAdd(&s_h[0 * kBins + (d & 255)], 1u);
-      atomicAdd(&s_h[1 * kBins + ((d >> 8) & 255)], 1u);
-      atomicAdd(&s_h[2 * kBins + ((d >> 16) & 255)], 1u);
-      atomicAdd(&s_h[3 * kBins + (d >> 24)], 1u);
-      atomicAdd(&s_h[4 * kBins + (s & 255)], 1u);
-      atomicAdd(&s_h[5 * kBins + ((s >> 8) & 255)], 1u);
-      atomicAdd(&s_h[6 * kBins + ((s >> 16) & 255)], 1u);
-      atomicAdd(&s_h[7 * kBins + (s >> 24)], 1u);
+    constexpr int R = 8;  // packets per thread per round, loads issued together
+    for (uint64_t i0 = start + threadIdx.x; i0 < end; i0 += (uint64_t)R * BLOCK) {
+      uint32_t sv[R], dv[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const uint64_t i = i0 + (uint64_t)k * BLOCK;
+        sv[k] = i < end ? src[i] : 0;
+        dv[k] = i < end ? dst[i] : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        if (i0 + (uint64_t)k * BLOCK >= end) break;
+        const uint32_t d = dv[k], s = sv[k];
+        atomicAdd(&s_h[0 * kBins + (d & 255)], 1u);
+        atomicAdd(&s_h[1 * kBins + ((d >> 8) & 255)], 1u);
+        atomicAdd(&s_h[2 * kBins + ((d >> 16) & 255)], 1u);
+        atomicAdd(&s_h[3 * kBins + (d >> 24)], 1u);
+        atomicAdd(&s_h[4 * kBins + (s & 255)], 1u);
+        atomicAdd(&s_h[5 * kBins + ((s >> 8) & 255)], 1u);
+        atomicAdd(&s_h[6 * kBins + ((s >> 16) & 255)], 1u);
+        atomicAdd(&s_h[7 * kBins + (s >> 24)], 1u);
+      }
     }
     __syncthreads();
     uint32_t *g = hist + (uint64_t)w * (kKeyDigits * kBins);
@@ -233,7 +247,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
     if (tid < kBins) {
       uint64_t excl = 0;
       if (t != first) {
-        excl = lb_walk(a.lb, kBins, tid, t, first);
+        excl = lb_walk4(a.lb, kBins, tid, t, first);
         lb_store(a.lb + (uint64_t)t * kBins + tid, kLbInc | (excl + s_tot[tid]));
       }
       s_gbase[tid] = seg_lo + a.base[(uint64_t)w * a.base_stride + tid] + excl;
@@ -256,21 +270,37 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// First index in (lo, hi] whose key differs from K, given keys[lo] == K and a
-// sorted array: galloping then bisection, O(log run length) reads.
+// First index in (lo, hi] whose key differs from K, given keys[lo] == K in a
+// sorted array (hi if none). The whole calling wave searches together: 64
+// probes per round trip (the next 64 positions, then 64 exponentially spaced
+// ones, then 64-way subdivision), so even a run of 2^30 equal keys takes a
+// handful of dependent loads. Every lane returns the same value.
 // ---------------------------------------------------------------------------
-__device__ uint64_t run_end(const uint64_t *keys, uint64_t lo, uint64_t hi, uint64_t K) {
-  uint64_t step = 1;
-  while (lo + step < hi && keys[lo + step] == K) {
-    lo += step;
-    step <<= 1;
+__device__ uint64_t run_end_wave(const uint64_t *keys, uint64_t lo, uint64_t hi, uint64_t K) {
+  const int lane = threadIdx.x & (kWave - 1);
+  {
+    const uint64_t p = lo + 1 + lane;
+    const uint64_t m = ballot64(p >= hi ? true : keys[p] != K);
+    if (m) return min(lo + 1 + (uint64_t)(__ffsll((long long)m) - 1), hi);
   }
-  uint64_t r = min(lo + step, hi);
-  while (r - lo > 1) {
-    const uint64_t mid = lo + (r - lo) / 2;
-    if (keys[mid] == K) lo = mid; else r = mid;
+  uint64_t L = lo + 64, R;  // keys[L] == K
+  {
+    const uint64_t p = L + (64ull << min(lane, 40));
+    const uint64_t m = ballot64(p >= hi ? true : keys[p] != K);
+    const int f = __ffsll((long long)m) - 1;  // some lane reaches hi
+    R = min(L + (64ull << f), hi);
+    if (f > 0) L += 64ull << (f - 1);
   }
-  return r;
+  while (R - L > 1) {
+    const uint64_t step = (R - L + 63) / 64;
+    const uint64_t p = L + step * (uint64_t)(lane + 1);
+    const uint64_t m = ballot64(p >= R ? true : keys[p] != K);
+    const int f = __ffsll((long long)m) - 1;
+    const uint64_t nR = min(L + step * (uint64_t)(f + 1), R);
+    L = L + step * (uint64_t)f;
+    R = nR;
+  }
+  return R;
 }
 
 // ---------------------------------------------------------------------------
@@ -291,10 +321,11 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
   constexpr int BLOCK = 256;
   constexpr int TILE = BLOCK * ITEMS;
   static_assert(ITEMS <= 32, "head masks are 32-bit");
+  static_assert(TILE <= 65536, "tile positions are 16-bit");
   __shared__ uint64_t s_k[TILE + 1];
-  __shared__ uint32_t s_hpos[TILE];
-  __shared__ uint32_t s_rpos[TILE];
-  __shared__ uint32_t s_rlr[TILE];
+  __shared__ uint16_t s_hpos[TILE];   // link head positions in the tile
+  __shared__ uint16_t s_rpos[TILE];   // row head positions
+  __shared__ uint16_t s_rlr[TILE];    // tile-local link rank of each row head
   __shared__ uint32_t s_ch[kColDigits * kBins];
   __shared__ uint64_t s_tmp[BLOCK / kWave];
   __shared__ uint64_t s_L0, s_R0, s_trail, s_base;
@@ -344,34 +375,36 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
 #pragma unroll
       for (int k = 0; k < ITEMS; ++k) {
         if (rmask & (1u << k)) {
-          s_rpos[jr] = p0 + k;
-          s_rlr[jr] = jl;  // a row head is also a link head: its link rank
+          s_rpos[jr] = (uint16_t)(p0 + k);
+          s_rlr[jr] = (uint16_t)jl;  // a row head is also a link head: its link rank
           ++jr;
         }
-        if (lmask & (1u << k)) s_hpos[jl++] = p0 + k;
+        if (lmask & (1u << k)) s_hpos[jl++] = (uint16_t)(p0 + k);
       }
     }
-    if (tid == 0) {
+    // end of the tile's last run, searched past the tile by wave 2; in place, the
+    // search must finish before this tile publishes (later tiles then write)
+    const bool in_place = a.ukeys == a.keys;
+    if (tid / kWave == 2) {
       uint64_t e = start + n;
       if (TL > 0 && e < seg_hi) {
         const uint64_t K = s_k[n];
-        if (a.keys[e] == K) e = run_end(a.keys, e, seg_hi, K);
+        if (a.keys[e] == K) e = run_end_wave(a.keys, e, seg_hi, K);
       }
-      s_trail = e;
+      if ((tid & (kWave - 1)) == 0) s_trail = e;
     }
-    __syncthreads();  // the search above is done before anything is published
-    if (tid < 2) {
-      const uint64_t mine = tid == 0 ? TL : TR;
-      uint64_t *slot = a.lb + 2ull * t + tid;
+    if (in_place) __syncthreads();
+    if (tid < 2) lb_store(a.lb + 2ull * t + tid, (t == 0 ? kLbInc : kLbAgg) | (tid == 0 ? TL : TR));
+    if (tid < 2 * kWave) {  // wave 0 resolves the link channel, wave 1 the row channel
+      const uint32_t ch = tid / kWave;
       uint64_t excl = 0;
-      if (t == 0) {
-        lb_store(slot, kLbInc | mine);
-      } else {
-        lb_store(slot, kLbAgg | mine);
-        excl = lb_walk(a.lb, 2, tid, t, 0);
-        lb_store(slot, kLbInc | (excl + mine));
+      if (t > 0) {
+        excl = lb_walk_wave(a.lb, 2, ch, t);
+        if ((tid & (kWave - 1)) == 0) lb_store(a.lb + 2ull * t + ch, kLbInc | (excl + (ch ? TR : TL)));
       }
-      if (tid == 0) s_L0 = excl; else s_R0 = excl;
+      if ((tid & (kWave - 1)) == 0) {
+        if (ch == 0) s_L0 = excl; else s_R0 = excl;
+      }
     }
     __syncthreads();
     const uint64_t L0 = s_L0, R0 = s_R0, trail = s_trail;
@@ -468,9 +501,10 @@ template <int ITEMS, int MODE>
 __global__ __launch_bounds__(256) void k_runs(RunArgs a) {
   constexpr int BLOCK = 256;
   constexpr int TILE = BLOCK * ITEMS;
-  __shared__ uint64_t s_g[TILE + 1];   // group key
+  static_assert(TILE <= 65536, "tile positions are 16-bit");
+  __shared__ uint64_t s_g[TILE + 1];   // group key (a 32-bit address; 2^32 marks "none")
   __shared__ uint32_t s_v[TILE];       // value (< 2^32)
-  __shared__ uint32_t s_hp[TILE];      // head local positions
+  __shared__ uint16_t s_hp[TILE];      // head local positions
   __shared__ uint32_t s_hv[TILE];      // tile-local exclusive value prefix at head
   __shared__ uint32_t s_ch[kColDigits * kBins];
   __shared__ uint64_t s_tmp[BLOCK / kWave];
@@ -533,25 +567,24 @@ __global__ __launch_bounds__(256) void k_runs(RunArgs a) {
       for (int k = 0; k < ITEMS; ++k) {
         const uint32_t p = p0 + k;
         if (hmask & (1u << k)) {
-          s_hp[jh] = p;
+          s_hp[jh] = (uint16_t)p;
           s_hv[jh] = run;
           ++jh;
         }
         if (p < n) run += s_v[p];
       }
     }
-    if (tid < 2) {
-      const uint64_t mine = tid == 0 ? TH : TV;
-      uint64_t *slot = a.lb + 2ull * t + tid;
+    if (tid < 2) lb_store(a.lb + 2ull * t + tid, (t == 0 ? kLbInc : kLbAgg) | (tid == 0 ? TH : TV));
+    if (tid < 2 * kWave) {  // wave 0: head channel, wave 1: value channel
+      const uint32_t ch = tid / kWave;
       uint64_t excl = 0;
-      if (t == 0) {
-        lb_store(slot, kLbInc | mine);
-      } else {
-        lb_store(slot, kLbAgg | mine);
-        excl = lb_walk(a.lb, 2, tid, t, 0);
-        lb_store(slot, kLbInc | (excl + mine));
+      if (t > 0) {
+        excl = lb_walk_wave(a.lb, 2, ch, t);
+        if ((tid & (kWave - 1)) == 0) lb_store(a.lb + 2ull * t + ch, kLbInc | (excl + (ch ? TV : TH)));
       }
-      if (tid == 0) s_H0 = excl; else s_V0 = excl;
+      if ((tid & (kWave - 1)) == 0) {
+        if (ch == 0) s_H0 = excl; else s_V0 = excl;
+      }
     }
     __syncthreads();
     const uint64_t H0 = s_H0, V0 = s_V0;
@@ -585,38 +618,46 @@ __global__ __launch_bounds__(256) void k_runs(RunArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-segment maxima of consecutive-head differences (DPP-style wave max,
-// then one 64-bit atomic per wave; per-lane atomics only where a wave
-// straddles a segment boundary).
+// Per-segment maxima of consecutive-head differences. Each workgroup takes one
+// contiguous range of heads, splits it at segment boundaries (usually none or
+// one), reduces each piece with wave and LDS maxima and issues one 64-bit
+// atomic per piece and field.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_segmax(const uint64_t *a, const uint64_t *b,
                                                 const uint64_t *head_off, uint32_t W,
                                                 uint64_t *stats, int fa, int fb) {
+  __shared__ uint64_t s_ma[4], s_mb[4];
   const uint64_t total = head_off[W];
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < total; base += stride) {
-    const uint64_t r = base + threadIdx.x;
-    const bool valid = r < total;
-    uint32_t w = 0;
-    uint64_t da = 0, db = 0;
-    if (valid) {
-      w = find_owner(head_off, W, r);
-      da = a[r + 1] - a[r];
-      db = b[r + 1] - b[r];
+  const uint64_t chunk = (total + gridDim.x - 1) / gridDim.x;
+  const uint64_t lo = blockIdx.x * chunk, hi = min(lo + chunk, total);
+  if (lo >= hi) return;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const uint32_t w0 = find_owner(head_off, W, lo), w1 = find_owner(head_off, W, hi - 1);
+  for (uint32_t w = w0; w <= w1; ++w) {
+    const uint64_t plo = max(lo, head_off[w]), phi = min(hi, head_off[w + 1]);
+    if (plo >= phi) continue;  // uniform: every thread sees the same bounds
+    uint64_t ma = 0, mb = 0;
+    for (uint64_t r = plo + tid; r < phi; r += 256) {
+      const uint64_t da = a[r + 1] - a[r], db = b[r + 1] - b[r];
+      ma = ma > da ? ma : da;
+      mb = mb > db ? mb : db;
     }
-    const uint64_t vm = ballot64(valid);
-    const int lead = __ffsll((long long)vm) - 1;  // lowest valid lane (vm != 0 here)
-    const uint32_t w0 = __shfl(w, lead, kWave);
-    if (ballot64(valid && w == w0) == vm) {
-      const uint64_t ma = wave_max(da), mb = wave_max(db);
-      if ((threadIdx.x & (kWave - 1)) == (uint32_t)lead) {
-        atomicMax((unsigned long long *)&stats[(uint64_t)w0 * 8 + fa], (unsigned long long)ma);
-        atomicMax((unsigned long long *)&stats[(uint64_t)w0 * 8 + fb], (unsigned long long)mb);
+    ma = wave_max(ma);
+    mb = wave_max(mb);
+    if (lane == 0) {
+      s_ma[wv] = ma;
+      s_mb[wv] = mb;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int q = 1; q < 4; ++q) {
+        ma = ma > s_ma[q] ? ma : s_ma[q];
+        mb = mb > s_mb[q] ? mb : s_mb[q];
       }
-    } else if (valid) {
-      atomicMax((unsigned long long *)&stats[(uint64_t)w * 8 + fa], (unsigned long long)da);
-      atomicMax((unsigned long long *)&stats[(uint64_t)w * 8 + fb], (unsigned long long)db);
+      atomicMax((unsigned long long *)&stats[(uint64_t)w * 8 + fa], (unsigned long long)ma);
+      atomicMax((unsigned long long *)&stats[(uint64_t)w * 8 + fb], (unsigned long long)mb);
     }
+    __syncthreads();
   }
 }
 
@@ -784,18 +825,17 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
     if (underflow) atomicOr(&g_status, 1);
     uint64_t tot;
     const uint64_t x = block_excl_scan<BLOCK>(keep, s_tmp, &tot);
-    if (tid == 0) {
-      uint64_t *slot = a.lb + t;
+    if (tid == 0) lb_store(a.lb + t, (t == 0 ? kLbInc : kLbAgg) | tot);
+    if (tid < kWave) {
       uint64_t excl = 0;
-      if (t == 0) {
-        lb_store(slot, kLbInc | tot);
-      } else {
-        lb_store(slot, kLbAgg | tot);
-        excl = lb_walk(a.lb, 1, 0, t, 0);
-        lb_store(slot, kLbInc | (excl + tot));
+      if (t > 0) {
+        excl = lb_walk_wave(a.lb, 1, 0, t);
+        if (tid == 0) lb_store(a.lb + t, kLbInc | (excl + tot));
       }
-      s_L0 = excl;
-      if (t == tiles - 1) *a.nc = excl + tot;
+      if (tid == 0) {
+        s_L0 = excl;
+        if (t == tiles - 1) *a.nc = excl + tot;
+      }
     }
     __syncthreads();  // everyone is done reading s_k / s_c
     {
@@ -822,6 +862,22 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
 // ===========================================================================
 // host launchers
 // ===========================================================================
+thread_local int tl_timing_kind = -1;
+
+// Launch, with start/stop events taken by the dispatch itself when timing is on
+// (hipExtLaunchKernelGGL), so a recorded duration is the kernel's own.
+#define NS_LAUNCH(kernel, grid, block, stream, ...)                                        \
+  do {                                                                                     \
+    hipEvent_t e0_ = nullptr, e1_ = nullptr;                                               \
+    if (tl_timing_kind >= 0 && hipEventCreate(&e0_) == hipSuccess &&                        \
+        hipEventCreate(&e1_) == hipSuccess) {                                              \
+      hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, e0_, e1_, 0, __VA_ARGS__);      \
+      record_timing(tl_timing_kind, e0_, e1_);                                             \
+    } else {                                                                               \
+      hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__);                     \
+    }                                                                                      \
+  } while (0)
+
 namespace {
 
 int device_id() {
@@ -861,25 +917,25 @@ uint32_t clamp_grid(uint64_t want, uint64_t cap) {
 hipError_t launch_fill64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const uint32_t g = clamp_grid((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_fill64, dim3(g), dim3(256), 0, s, p, n, v);
+  NS_LAUNCH(k_fill64, dim3(g), dim3(256), s, p, n, v);
   return hipGetLastError();
 }
 
 hipError_t launch_fill32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const uint32_t g = clamp_grid((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_fill32, dim3(g), dim3(256), 0, s, p, n, v);
+  NS_LAUNCH(k_fill32, dim3(g), dim3(256), s, p, n, v);
   return hipGetLastError();
 }
 
 hipError_t launch_seg1(uint64_t *seg, const uint64_t *n_dev, uint64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_seg1, dim3(1), dim3(64), 0, s, seg, n_dev, n);
+  NS_LAUNCH(k_seg1, dim3(1), dim3(64), s, seg, n_dev, n);
   return hipGetLastError();
 }
 
 hipError_t launch_tiles(const uint64_t *seg_off, uint32_t W, uint32_t ta, uint64_t *oa,
                         uint32_t tb, uint64_t *ob, uint32_t tc, uint64_t *oc, hipStream_t s) {
-  hipLaunchKernelGGL(k_tiles, dim3(1), dim3(1024), 0, s, seg_off, W, ta, oa, tb, ob, tc, oc);
+  NS_LAUNCH(k_tiles, dim3(1), dim3(1024), s, seg_off, W, ta, oa, tb, ob, tc, oc);
   return hipGetLastError();
 }
 
@@ -889,7 +945,7 @@ hipError_t launch_hist_packets(const uint32_t *src, const uint32_t *dst, const u
   static uint64_t cap[64];
   const int d = device_id();
   if (!cap[d]) cap[d] = resident(k_hist_packets<256>, 256);
-  hipLaunchKernelGGL(k_hist_packets<256>, dim3(clamp_grid(max_tiles, cap[d])), dim3(256), 0, s,
+  NS_LAUNCH(k_hist_packets<256>, dim3(clamp_grid(max_tiles, cap[d])), dim3(256), s,
                      src, dst, seg_off, tile_off, W, hist);
   return hipGetLastError();
 }
@@ -897,7 +953,7 @@ hipError_t launch_hist_packets(const uint32_t *src, const uint32_t *dst, const u
 hipError_t launch_hist_scan(const uint32_t *hist, uint32_t *base, uint64_t rows, hipStream_t s) {
   if (rows == 0) return hipSuccess;
   const uint64_t blocks = (rows + 3) / 4;  // 4 waves per block
-  hipLaunchKernelGGL(k_hist_scan, dim3((uint32_t)blocks), dim3(256), 0, s, hist, base, rows);
+  NS_LAUNCH(k_hist_scan, dim3((uint32_t)blocks), dim3(256), s, hist, base, rows);
   return hipGetLastError();
 }
 
@@ -906,7 +962,7 @@ static hipError_t pass_impl(const PassArgs &a, uint64_t max_tiles, hipStream_t s
   static uint64_t cap[64];
   const int d = device_id();
   if (!cap[d]) cap[d] = resident(k_pass<B, I, P>, B);
-  hipLaunchKernelGGL((k_pass<B, I, P>), dim3(clamp_grid(max_tiles, cap[d])), dim3(B), 0, s, a);
+  NS_LAUNCH((k_pass<B, I, P>), dim3(clamp_grid(max_tiles, cap[d])), dim3(B), s, a);
   return hipGetLastError();
 }
 
@@ -924,7 +980,7 @@ static hipError_t rle_impl(const RleArgs &a, uint64_t max_tiles, hipStream_t s) 
   static uint64_t cap[64];
   const int d = device_id();
   if (!cap[d]) cap[d] = resident(k_rle<I>, 256);
-  hipLaunchKernelGGL(k_rle<I>, dim3(clamp_grid(max_tiles, cap[d])), dim3(256), 0, s, a);
+  NS_LAUNCH(k_rle<I>, dim3(clamp_grid(max_tiles, cap[d])), dim3(256), s, a);
   return hipGetLastError();
 }
 
@@ -939,7 +995,7 @@ static hipError_t runs_impl(const RunArgs &a, uint64_t max_tiles, hipStream_t s)
   static uint64_t cap[64];
   const int d = device_id();
   if (!cap[d]) cap[d] = resident(k_runs<I, M>, 256);
-  hipLaunchKernelGGL((k_runs<I, M>), dim3(clamp_grid(max_tiles, cap[d])), dim3(256), 0, s, a);
+  NS_LAUNCH((k_runs<I, M>), dim3(clamp_grid(max_tiles, cap[d])), dim3(256), s, a);
   return hipGetLastError();
 }
 
@@ -953,8 +1009,8 @@ hipError_t launch_runs(const ScanShape &sh, int mode, const RunArgs &a, uint64_t
 hipError_t launch_segmax(const uint64_t *a, const uint64_t *b, const uint64_t *head_off,
                          uint32_t W, uint64_t max_heads, uint64_t *stats, int fa, int fb,
                          hipStream_t s) {
-  const uint32_t g = clamp_grid((max_heads + 255) / 256, 8ull * cu_count());
-  hipLaunchKernelGGL(k_segmax, dim3(g), dim3(256), 0, s, a, b, head_off, W, stats, fa, fb);
+  const uint32_t g = clamp_grid((max_heads + 1023) / 1024, 4ull * cu_count());
+  NS_LAUNCH(k_segmax, dim3(g), dim3(256), s, a, b, head_off, W, stats, fa, fb);
   return hipGetLastError();
 }
 
@@ -963,7 +1019,7 @@ hipError_t launch_finalize(const uint64_t *seg_off, const uint64_t *link_off,
                            uint64_t *stats, hipStream_t s) {
   if (W == 0) return hipSuccess;
   const uint32_t g = clamp_grid((W + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, seg_off, link_off, row_off, col_off, W,
+  NS_LAUNCH(k_finalize, dim3(g), dim3(256), s, seg_off, link_off, row_off, col_off, W,
                      stats);
   return hipGetLastError();
 }
@@ -971,7 +1027,7 @@ hipError_t launch_finalize(const uint64_t *seg_off, const uint64_t *link_off,
 hipError_t launch_finalize_matrix(const uint64_t *row_hval, const uint64_t *row_off,
                                   const uint64_t *col_off, const uint64_t *nnz, uint64_t *stats,
                                   hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_matrix, dim3(1), dim3(64), 0, s, row_hval, row_off, col_off, nnz,
+  NS_LAUNCH(k_finalize_matrix, dim3(1), dim3(64), s, row_hval, row_off, col_off, nnz,
                      stats);
   return hipGetLastError();
 }
@@ -980,7 +1036,7 @@ hipError_t launch_merge(const MergeArgs &a, uint64_t max_tiles, hipStream_t s) {
   static uint64_t cap[64];
   const int d = device_id();
   if (!cap[d]) cap[d] = resident(k_merge, 256);
-  hipLaunchKernelGGL(k_merge, dim3(clamp_grid(max_tiles, cap[d])), dim3(256), 0, s, a);
+  NS_LAUNCH(k_merge, dim3(clamp_grid(max_tiles, cap[d])), dim3(256), s, a);
   return hipGetLastError();
 }
 

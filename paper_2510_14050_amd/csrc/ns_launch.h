@@ -133,4 +133,10 @@ hipError_t launch_merge(const MergeArgs &a, uint64_t max_tiles, hipStream_t s);
 // device error word
 hipError_t read_and_clear_status(int *host_status);
 
+// Kernel timing: while tl_timing_kind >= 0, every launch on this thread takes
+// start/stop events in its dispatch and hands them to record_timing (defined by
+// the API layer, which owns the events).
+extern thread_local int tl_timing_kind;
+void record_timing(int kind, hipEvent_t start, hipEvent_t stop);
+
 }  // namespace ns
