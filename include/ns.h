@@ -158,8 +158,38 @@ int ns_batch_stats_eager(const uint32_t *src, const uint32_t *dst, const uint64_
                          ns_batch_matrices_t *win_out, const ns_tuning_t *tune, void *ws,
                          uint64_t ws_bytes, void *stream);
 
+/* Rolling aggregate for serving (the running union-add of the windows added
+ * minus the windows removed), kept in device hash tables so that an update
+ * costs time proportional to the entries of the windows involved, not to the
+ * aggregate. Layout: one caller-owned device buffer `mem` of `bytes` >=
+ * ns_rolling_size(...); link_slots and address_slots are powers of two (hash
+ * slots for distinct links and for distinct sources / destinations; keep live
+ * entries plus those added since the last compaction below ~60% of them). The
+ * state holds fewer than 2^32 packets. */
+typedef struct {
+  void *mem;
+  uint64_t bytes;
+  uint64_t link_slots;
+  uint64_t address_slots;
+} ns_rolling_t;
+
+/* Bytes of state for the given slot counts (host only). */
+int ns_rolling_size(uint64_t link_slots, uint64_t address_slots, uint64_t *bytes);
+/* Clears the state to the empty aggregate. */
+int ns_rolling_init(const ns_rolling_t *r, void *stream);
+/* Applies A <- A + add - remove (either may be NULL; remove must be part of
+ * A, as a window that entered earlier) and writes the eight quantities of the
+ * new A to *out (device), all exactly as ns_stats would compute them on the
+ * matrix A. A full table or a remove that is not part of A is reported by
+ * ns_device_status (NS_ERR_CAPACITY / NS_ERR_UNDERFLOW). */
+int ns_rolling_update(const ns_rolling_t *r, const ns_matrix_t *add, const ns_matrix_t *remove,
+                      ns_stats_t *out, void *stream);
+/* Copies the live entries of `from` into `to` (same slot counts), dropping the
+ * tombstones of links, sources and destinations whose counts returned to 0. */
+int ns_rolling_compact(const ns_rolling_t *from, const ns_rolling_t *to, void *stream);
+
 /* Synchronises `stream`, then reads and clears the current device's error
- * word: *status (host) = NS_OK or NS_ERR_UNDERFLOW. */
+ * word: *status (host) = NS_OK, NS_ERR_UNDERFLOW or NS_ERR_CAPACITY. */
 int ns_device_status(void *stream, int *status);
 
 /* Destroys every cached HIP graph (call before freeing buffers a cached graph

@@ -677,6 +677,73 @@ int ns_batch_stats(const uint32_t *src, const uint32_t *dst, const uint64_t *off
   return NS_OK;
 }
 
+int ns_rolling_size(uint64_t link_slots, uint64_t address_slots, uint64_t *bytes) {
+  if (!bytes) return NS_ERR_INVALID_ARG;
+  *bytes = roll_bytes(link_slots, address_slots);
+  return NS_OK;
+}
+
+static int rolling_check(const ns_rolling_t *r) {
+  if (!r || !r->mem || (reinterpret_cast<uintptr_t>(r->mem) % kAlign) != 0) return NS_ERR_INVALID_ARG;
+  const uint64_t l = r->link_slots, a = r->address_slots;
+  if (l < 64 || a < 64 || (l & (l - 1)) || (a & (a - 1))) return NS_ERR_INVALID_ARG;
+  if (r->bytes < roll_bytes(l, a)) return NS_ERR_WORKSPACE;
+  return NS_OK;
+}
+
+int ns_rolling_init(const ns_rolling_t *r, void *stream) {
+  int rc = rolling_check(r);
+  if (rc) return rc;
+  const RollTables t = roll_tables(r->mem, r->link_slots, r->address_slots);
+  HIP_TRY(launch_roll_clear(t, static_cast<hipStream_t>(stream)));
+  return NS_OK;
+}
+
+int ns_rolling_update(const ns_rolling_t *r, const ns_matrix_t *add, const ns_matrix_t *remove,
+                      ns_stats_t *out, void *stream) {
+  int rc = rolling_check(r);
+  if (rc) return rc;
+  if (!out) return NS_ERR_INVALID_ARG;
+  const ns_matrix_t *ms[2] = {add, remove};
+  for (const ns_matrix_t *m : ms)
+    if (m && (!m->keys || !m->counts || !m->nnz)) return NS_ERR_INVALID_ARG;
+  const RollTables t = roll_tables(r->mem, r->link_slots, r->address_slots);
+  RollDelta d{};
+  uint64_t items = 0;
+  if (add) {
+    d.add_keys = add->keys;
+    d.add_counts = add->counts;
+    d.add_nnz = add->nnz;
+    d.add_cap = add->capacity < add->packets ? add->capacity : add->packets;
+    items += d.add_cap;
+  }
+  if (remove) {
+    d.rem_keys = remove->keys;
+    d.rem_counts = remove->counts;
+    d.rem_nnz = remove->nnz;
+    d.rem_cap = remove->capacity < remove->packets ? remove->capacity : remove->packets;
+    items += d.rem_cap;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(timed(K_MERGE, s, [&] { return launch_roll_update(t, d, items, s); }));
+  HIP_TRY(timed(K_SEGMAX, s, [&] { return launch_roll_stats(t, reinterpret_cast<uint64_t *>(out), s); }));
+  return NS_OK;
+}
+
+int ns_rolling_compact(const ns_rolling_t *from, const ns_rolling_t *to, void *stream) {
+  int rc = rolling_check(from);
+  if (rc) return rc;
+  rc = rolling_check(to);
+  if (rc) return rc;
+  if (from->link_slots != to->link_slots || from->address_slots != to->address_slots ||
+      from->mem == to->mem)
+    return NS_ERR_INVALID_ARG;
+  const RollTables a = roll_tables(from->mem, from->link_slots, from->address_slots);
+  const RollTables b = roll_tables(to->mem, to->link_slots, to->address_slots);
+  HIP_TRY(launch_roll_compact(a, b, static_cast<hipStream_t>(stream)));
+  return NS_OK;
+}
+
 int ns_device_status(void *stream, int *status) {
   if (!status) return NS_ERR_INVALID_ARG;
   HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));

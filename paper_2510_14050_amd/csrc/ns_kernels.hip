@@ -14,7 +14,7 @@
 
 namespace ns {
 
-__device__ int g_status;  // NS_OK (0) or NS_ERR_UNDERFLOW (-5), set by the merge
+__device__ int g_status;  // bit 0: subtraction below zero; bit 1: a hash table is full
 
 // ---------------------------------------------------------------------------
 // small utilities
@@ -1047,8 +1047,11 @@ hipError_t read_and_clear_status(int *host_status) {
   if (e != hipSuccess) return e;
   const int zero = 0;
   e = hipMemcpyToSymbol(HIP_SYMBOL(g_status), &zero, sizeof(int), 0, hipMemcpyHostToDevice);
-  *host_status = v ? -5 : 0;
+  *host_status = (v & 1) ? -5 : (v & 2) ? -2 : 0;
   return e;
 }
 
 }  // namespace ns
+
+// the rolling-aggregate kernels share this translation unit (and g_status)
+#include "ns_rolling.hip"

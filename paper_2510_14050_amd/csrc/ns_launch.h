@@ -130,7 +130,38 @@ struct MergeArgs {
 };
 hipError_t launch_merge(const MergeArgs &a, uint64_t max_tiles, hipStream_t s);
 
-// device error word
+// --- rolling aggregate (serving) ----------------------------------------------------
+struct RollHeader {
+  uint64_t links, sources, dests, packets;  // live counts
+  uint64_t scan[4];                         // maxima found by the last scan
+  uint32_t special_count;                   // count of the link key 0xFFFFFFFFFFFFFFFF
+  uint32_t pad;
+};
+struct RollTables {
+  RollHeader *hdr;
+  uint64_t link_cap, addr_cap;  // slots, powers of two
+  uint64_t *link_keys;
+  uint32_t *link_cnt;
+  uint64_t *src_keys;
+  uint32_t *src_pk, *src_fan;
+  uint64_t *dst_keys;
+  uint32_t *dst_pk, *dst_fan;
+};
+struct RollDelta {
+  const uint64_t *add_keys, *add_counts, *add_nnz;
+  uint64_t add_cap;
+  const uint64_t *rem_keys, *rem_counts, *rem_nnz;
+  uint64_t rem_cap;
+};
+uint64_t roll_bytes(uint64_t link_cap, uint64_t addr_cap);
+RollTables roll_tables(void *mem, uint64_t link_cap, uint64_t addr_cap);
+hipError_t launch_roll_clear(const RollTables &t, hipStream_t s);
+hipError_t launch_roll_update(const RollTables &t, const RollDelta &d, uint64_t max_items,
+                              hipStream_t s);
+hipError_t launch_roll_stats(const RollTables &t, uint64_t *out, hipStream_t s);
+hipError_t launch_roll_compact(const RollTables &from, const RollTables &to, hipStream_t s);
+
+// device error word: bit 0 underflow, bit 1 capacity (hash table full)
 hipError_t read_and_clear_status(int *host_status);
 
 // Kernel timing: while tl_timing_kind >= 0, every launch on this thread takes

@@ -51,13 +51,19 @@ class Tuning(ctypes.Structure):
                 ("digit_bits", ctypes.c_uint32), ("scan_items", ctypes.c_uint32)]
 
 
+class RollingView(ctypes.Structure):
+    _fields_ = [("mem", ctypes.c_void_p), ("bytes", ctypes.c_uint64),
+                ("link_slots", ctypes.c_uint64), ("address_slots", ctypes.c_uint64)]
+
+
 class BatchMatricesView(ctypes.Structure):
     _fields_ = [("keys", ctypes.c_void_p), ("counts", ctypes.c_void_p),
                 ("nnz", ctypes.c_void_p), ("capacity", ctypes.c_uint64)]
 
 
 EXPORTS = ("ns_workspace_size", "ns_build_matrix", "ns_accumulate", "ns_stats",
-           "ns_batch_stats", "ns_batch_stats_eager", "ns_device_status", "ns_release_graphs",
+           "ns_batch_stats", "ns_batch_stats_eager", "ns_rolling_size", "ns_rolling_init",
+           "ns_rolling_update", "ns_rolling_compact", "ns_device_status", "ns_release_graphs",
            "ns_timing_enable", "ns_timing_reset", "ns_timing_read",
            "ns_error_string", "ns_version")
 
@@ -86,6 +92,11 @@ def load(path: str = LIB_PATH):
              ctypes.POINTER(Tuning), P, U64, P]
     lib.ns_batch_stats.argtypes = batch
     lib.ns_batch_stats_eager.argtypes = batch
+    PR = ctypes.POINTER(RollingView)
+    lib.ns_rolling_size.argtypes = [U64, U64, ctypes.POINTER(U64)]
+    lib.ns_rolling_init.argtypes = [PR, P]
+    lib.ns_rolling_update.argtypes = [PR, PM, PM, P, P]
+    lib.ns_rolling_compact.argtypes = [PR, PR, P]
     lib.ns_device_status.argtypes = [P, ctypes.POINTER(I)]
     lib.ns_release_graphs.argtypes = []
     lib.ns_timing_enable.argtypes = [I]
@@ -276,6 +287,46 @@ def batch_stats(src, dst, offsets, out, ws: Workspace, agg: Matrix | None = None
     if agg is not None:
         agg.packets = int(av.packets)
     return out
+
+
+class RollingState:
+    """Device hash-table state of a rolling aggregate (ns_rolling_*)."""
+
+    def __init__(self, link_slots: int = 1 << 25, address_slots: int = 1 << 23, device="cuda",
+                 stream=None):
+        torch = _torch()
+        out = ctypes.c_uint64()
+        _check(load().ns_rolling_size(link_slots, address_slots, ctypes.byref(out)),
+               "ns_rolling_size")
+        self.nbytes = int(out.value)
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.link_slots, self.address_slots = int(link_slots), int(address_slots)
+        self.clear(stream)
+
+    def view(self) -> RollingView:
+        return RollingView(self.buf.data_ptr(), self.nbytes, self.link_slots, self.address_slots)
+
+    def clear(self, stream=None):
+        v = self.view()
+        _check(load().ns_rolling_init(ctypes.byref(v), _stream(stream)), "ns_rolling_init")
+
+
+def rolling_update(state: RollingState, add: Matrix | None, remove: Matrix | None, out,
+                   stream=None):
+    """A <- A + add - remove on the rolling state; the eight quantities of A into out."""
+    r = state.view()
+    a = add.view() if add is not None else None
+    b = remove.view() if remove is not None else None
+    _check(load().ns_rolling_update(ctypes.byref(r), ctypes.byref(a) if a is not None else None,
+                                    ctypes.byref(b) if b is not None else None, _ptr(out),
+                                    _stream(stream)), "ns_rolling_update")
+    return out
+
+
+def rolling_compact(src: RollingState, dst: RollingState, stream=None):
+    a, b = src.view(), dst.view()
+    _check(load().ns_rolling_compact(ctypes.byref(a), ctypes.byref(b), _stream(stream)),
+           "ns_rolling_compact")
 
 
 def device_status(stream=None) -> int:

@@ -7,7 +7,11 @@ arena for their packets, a matrix arena for their traffic matrices), grouped
 into one micro-batch and submitted as one batched call on the build stream.
 The rolling chain (add the new window's matrix, subtract the window that left
 the ring, reduce the aggregate) runs in arrival order on a second stream and
-overlaps the next micro-batch's build. The rolling aggregate at arrival k is
+overlaps the next micro-batch's build. The rolling aggregate lives in device
+hash tables (ns_rolling_update), so an arrival costs time proportional to the
+two windows involved; mode="merge" keeps it as a sorted matrix updated by
+union-add and subtract (ns_accumulate + ns_stats) instead, whose cost grows
+with the aggregate. The rolling aggregate at arrival k is
 over windows max(0, k-ring+1)..k by arrival sequence, whatever the batching.
 
 Latency of an arrival = time its two result rows are on the host minus its
@@ -84,6 +88,7 @@ class ServeReport:
     batches: list = field(default_factory=list)      # windows per admitted micro-batch
     max_in_flight: int = 0                           # arrivals admitted, not yet on the host
     elapsed: float = 0.0
+    compactions: int = 0
     build_spans: list = field(default_factory=list)  # (batch, t_start_ms, t_end_ms) on device
     roll_spans: list = field(default_factory=list)
 
@@ -130,9 +135,12 @@ class Server:
     """
 
     def __init__(self, ring: int = 1024, max_window: int = 1 << 17, max_batch: int = 16,
-                 budget_bytes: int = 4 << 30, device="cuda", timing: bool = False):
+                 budget_bytes: int = 4 << 30, device="cuda", timing: bool = False,
+                 mode: str = "hash", link_slots: int = 1 << 25, address_slots: int = 1 << 23):
         import torch
         self.torch = torch
+        assert mode in ("hash", "merge")
+        self.mode = mode
         self.ring, self.max_window, self.max_batch = ring, max_window, max_batch
         self.timing = timing
         self.dev = d = torch.device(device)
@@ -148,12 +156,18 @@ class Server:
         self.pin_dst = torch.empty(self.stage_cap, dtype=torch.int32).pin_memory()
         self.mat_keys = torch.empty(self.mat_cap, dtype=torch.int64, device=d)
         self.mat_counts = torch.empty(self.mat_cap, dtype=torch.int64, device=d)
-        self.roll_cap = ring * max_window + max_window
-        self.acc = [ns.Matrix(self.roll_cap, device=d) for _ in range(3)]
         self.ws_build = ns.Workspace(batch_pk, max_batch, device=d)
-        self.ws_roll = ns.Workspace(self.roll_cap + max_window, 1, device=d)
         self.s_build = torch.cuda.Stream(device=d)
         self.s_roll = torch.cuda.Stream(device=d)
+        if mode == "merge":
+            self.roll_cap = ring * max_window + max_window
+            self.acc = [ns.Matrix(self.roll_cap, device=d) for _ in range(3)]
+            self.ws_roll = ns.Workspace(self.roll_cap + max_window, 1, device=d)
+        else:
+            self.ws_roll = ns.Workspace(max_window, 1, device=d)
+            self.states = [ns.RollingState(link_slots, address_slots, device=d, stream=self.s_roll)
+                           for _ in range(2)]
+            self.link_slots, self.address_slots = link_slots, address_slots
         self.slots = 8 * max_batch + 64     # result rows in flight (ring buffer by sequence)
         self.win_dev = torch.zeros((self.slots, 8), dtype=torch.int64, device=d)
         self.roll_dev = torch.zeros((self.slots, 8), dtype=torch.int64, device=d)
@@ -220,15 +234,22 @@ class Server:
                 self.win_dev[k].copy_(outs[i])
                 win = wm.window(i, int(off[i]), sizes[i])
                 st.views.append((seq, win, i == W - 1))
-                st.cur = self._accumulate(st, st.cur, win, 1)
+                old = None
                 if len(st.views) > self.ring:
                     _, old, last_of_batch = st.views.popleft()
-                    st.cur = self._accumulate(st, st.cur, old, -1)
-                    if last_of_batch:               # its whole matrix region can go
-                        ev = torch.cuda.Event()
-                        ev.record(self.s_roll)
-                        st.mat_free.append(ev)
-                ns.stats(st.cur, self.roll_dev[k], self.ws_roll)
+                if self.mode == "merge":
+                    st.cur = self._accumulate(st, st.cur, win, 1)
+                    if old is not None:
+                        st.cur = self._accumulate(st, st.cur, old, -1)
+                else:
+                    ns.rolling_update(self.states[st.si], win, old, self.roll_dev[k])
+                    self._maybe_compact(st, seq)
+                if old is not None and last_of_batch:  # its whole matrix region can go
+                    ev = torch.cuda.Event()
+                    ev.record(self.s_roll)
+                    st.mat_free.append(ev)
+                if self.mode == "merge":
+                    ns.stats(st.cur, self.roll_dev[k], self.ws_roll)
                 self.win_host[k].copy_(self.win_dev[k], non_blocking=True)
                 self.roll_host[k].copy_(self.roll_dev[k], non_blocking=True)
                 ev = torch.cuda.Event(enable_timing=self.timing)
@@ -237,6 +258,29 @@ class Server:
         if self.timing:
             st.timed.append((bidx, ev_b0, built, ev_r0, done[-1]))
         return done
+
+    def _maybe_compact(self, st, seq: int):
+        """Move the rolling state into the other buffer, dropping tombstones, once
+        the slots possibly occupied in a table (live entries at the last
+        compaction plus one per packet added since) could pass 60% of it. Live
+        entries are bounded by the counts of the latest arrival already on the
+        host plus one per packet added after it, and by the packets in the ring."""
+        n = int(st.sizes[seq])
+        st.occ = [o + n for o in st.occ]
+        caps = (self.link_slots, self.address_slots, self.address_slots)
+        if all(o <= 0.6 * c for o, c in zip(st.occ, caps)):
+            return
+        kseq, known = st.known
+        added = int(st.csum[seq + 1] - st.csum[kseq + 1]) if kseq >= 0 else int(st.csum[seq + 1])
+        in_ring = int(st.csum[seq + 1] - st.csum[max(0, seq + 1 - self.ring)])
+        live = [min(k + added, in_ring) for k in known]
+        if any(lv > 0.5 * c for lv, c in zip(live, caps)):
+            raise RuntimeError("rolling aggregate outgrows its hash tables; raise the slot counts")
+        nxt = 1 - st.si
+        ns.rolling_compact(self.states[st.si], self.states[nxt])
+        st.si = nxt
+        st.occ = live
+        st.compactions += 1
 
     def _accumulate(self, st, cur, win, sign):
         nxt = next(m for m in self.acc if m is not cur and m is not st.prev)
@@ -263,6 +307,13 @@ class Server:
         st.views = collections.deque()
         st.cur, st.prev = self.empty, None
         st.timed = []
+        st.si, st.compactions = 0, 0
+        st.occ = [0, 0, 0]             # possibly occupied link / source / destination slots
+        st.known = (-1, (0, 0, 0))     # (seq, (links, sources, destinations)) seen on the host
+        st.sizes = np.array([w[0].size for w in windows], np.int64)
+        st.csum = np.concatenate([[0], np.cumsum(st.sizes)])
+        if self.mode == "hash":
+            self.states[0].clear(self.s_roll)
 
         inbox = collections.deque()
         lock = threading.Lock()
@@ -294,6 +345,8 @@ class Server:
                                       self.win_host[k].numpy().view(np.uint64).copy(),
                                       self.roll_host[k].numpy().view(np.uint64).copy(),
                                       t_arr, t, bidx)
+                rs = results[seq].rolling_stats
+                st.known = (seq, (int(rs[1]), int(rs[2]), int(rs[3])))
                 done_q.popleft()
                 completed[0] += 1
 
@@ -338,6 +391,7 @@ class Server:
         tf.join()
         torch.cuda.synchronize()
         report.elapsed = (max(r.t_done for r in results) - t_start) if n else 0.0
+        report.compactions = st.compactions
         if self.timing and st.timed:
             t0 = st.timed[0][1]
             for b, e0, e1, r0, r1 in st.timed:

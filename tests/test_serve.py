@@ -76,17 +76,19 @@ def rolling_want(windows, ring):
 
 
 @pytest.mark.gpu
-def test_serving_alone_and_in_the_mix():
+@pytest.mark.parametrize("mode", ["hash", "merge"])
+def test_serving_alone_and_in_the_mix(mode):
     import torch
     from paper_2510_14050_amd.serve import Server
     ring, n = 6, 40
     wins = small_windows(n)
     want_roll = rolling_want(wins, ring)
     want_win = [oracle.stats(s, d) for s, d in wins]
+    kw = dict(mode=mode, link_slots=1 << 15, address_slots=1 << 14)
     srv = Server(ring=ring, max_window=1 << 12, max_batch=4, budget_bytes=64 << 20,
-                 timing=True)
-    say("serve alone (max_batch 1, serial)")
-    alone = Server(ring=ring, max_window=1 << 12, max_batch=1, budget_bytes=64 << 20)
+                 timing=True, **kw)
+    say("serve alone (max_batch 1, serial)", mode)
+    alone = Server(ring=ring, max_window=1 << 12, max_batch=1, budget_bytes=64 << 20, **kw)
     rep_alone = alone.run(wins)
     say("serve in the mix (all arrive at once)")
     rep_burst = srv.run(wins)
@@ -105,6 +107,8 @@ def test_serving_alone_and_in_the_mix():
     assert rep_burst.device_overlap() >= 1 or max(rep_burst.batches) > 1
     s = rep_poisson.summary()
     assert s["p50_ms"] is not None and s["p99_ms"] >= s["p50_ms"]
+    if mode == "hash":  # the small tables forced compactions along the way
+        assert rep_burst.compactions >= 1
 
 
 @pytest.mark.gpu
@@ -117,7 +121,8 @@ def test_serving_memory_budget_gates_admission():
     want_roll = rolling_want(wins, ring)
     mw = 1 << 12
     budget = 16 * (ring + 2 * 2) * mw + 8 * 2 * mw
-    srv = Server(ring=ring, max_window=mw, max_batch=2, budget_bytes=budget)
+    srv = Server(ring=ring, max_window=mw, max_batch=2, budget_bytes=budget,
+                 link_slots=1 << 15, address_slots=1 << 14)
     rep = srv.run(wins)
     for k, r in enumerate(rep.results):
         assert r.rolling_stats.tolist() == want_roll[k].tolist(), k
