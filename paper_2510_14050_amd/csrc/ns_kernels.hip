@@ -189,29 +189,44 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
     uint32_t dig[ITEMS];
     uint32_t rank[ITEMS];
     const uint32_t wbase = wv * (kWave * ITEMS);
+    if (n == TILE) {  // full tile: unpredicated loads
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint32_t li = wbase + k * kWave + lane;
-      uint64_t x = 0;
-      if (li < n) {
-        if (PACKETS) x = pack_key(a.src[start + li], a.dst[start + li]);
-        else x = a.in[start + li];
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint64_t i = start + wbase + k * kWave + lane;
+        key[k] = PACKETS ? pack_key(a.src[i], a.dst[i]) : a.in[i];
+        dig[k] = (uint32_t)(key[k] >> shift) & 255u;
       }
-      key[k] = x;
-      dig[k] = (li < n) ? (uint32_t)(x >> shift) & 255u : kBins;
+    } else {
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t li = wbase + k * kWave + lane;
+        uint64_t x = 0;
+        if (li < n) {
+          if (PACKETS) x = pack_key(a.src[start + li], a.dst[start + li]);
+          else x = a.in[start + li];
+        }
+        key[k] = x;
+        dig[k] = (li < n) ? (uint32_t)(x >> shift) & 255u : kBins;
+      }
     }
-    // stable rank within the wave, in (k, lane) order = original order
+    // stable rank within the wave, in (k, lane) order = original order. The
+    // peer mask is built on 32-bit halves: for each digit bit, the ballot m is
+    // kept where this lane's bit is set and its complement where it is clear.
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const uint32_t d = dig[k];
       const bool valid = d < kBins;
-      uint64_t peers = ballot64(valid);
+      const uint64_t vm = ballot64(valid);
+      uint32_t plo = (uint32_t)vm, phi = (uint32_t)(vm >> 32);
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t m = ballot64(bit);
-        peers &= bit ? m : ~m;
+        // all ones where this lane's bit b is set, zero where it is clear
+        const uint32_t ext = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+        const uint64_t m = ballot64(ext != 0);
+        plo &= ~((uint32_t)m ^ ext);
+        phi &= ~((uint32_t)(m >> 32) ^ ext);
       }
+      const uint64_t peers = ((uint64_t)phi << 32) | plo;
       if (valid) {
         const uint32_t below = count_below(peers);
         const uint32_t old = s_wcnt[wv][d];
