@@ -47,10 +47,10 @@ Layout plan(uint64_t N, uint32_t W) {
   auto take = [&](uint64_t bytes) { const uint64_t at = o; o += up(bytes); return at; };
   L.tickets = take(kMaxTickets * 4);
   L.seg = take(W1 * 8);
-  L.t_sort = take(W1 * 8);
+  L.t_sort = take((W1 + 1) * 8);
   L.t_hist = take(W1 * 8);
   L.t_rle = take(W1 * 8);
-  L.t_csort = take(W1 * 8);
+  L.t_csort = take((W1 + 1) * 8);
   L.t_run = take(W1 * 8);
   L.link_off = take(W1 * 8);
   L.row_off = take(W1 * 8);
@@ -404,7 +404,10 @@ namespace {
 struct GraphCache {
   std::mutex mu;
   std::unordered_map<std::string, hipGraphExec_t> execs;
-  hipStream_t capture[64] = {};
+  hipStream_t capture[64] = {};   // capture streams per device (the second carries
+  hipStream_t capture2[64] = {};  // the aggregate pipeline inside the graph)
+  hipEvent_t fork[64] = {};
+  hipEvent_t join[64] = {};
 };
 
 GraphCache &cache() {
@@ -424,8 +427,34 @@ struct BatchArgs {
   Shapes sh;
 };
 
-int enqueue_batch(const BatchArgs &b, Ws &ws, hipStream_t s) {
+// Per-window pipeline on `s` with workspace `ws`; the aggregate pipeline on
+// `s2` with workspace `ws2` (its own tickets, histograms, look-back words and
+// buffers). With s2 != s the aggregate forks off `s` through an event and joins
+// back, so the two independent pipelines overlap (also inside a captured graph).
+int enqueue_batch(const BatchArgs &b, Ws &ws, Ws &ws2, hipStream_t s, hipStream_t s2,
+                  hipEvent_t fork, hipEvent_t join) {
   HIP_TRY(launch_fill32(ws.at<uint32_t>(ws.L.tickets), kMaxTickets, 0, s));
+  const bool split = b.agg && s2 != s;
+  if (split) {
+    HIP_TRY(hipEventRecord(fork, s));
+    HIP_TRY(hipStreamWaitEvent(s2, fork, 0));
+  }
+  if (b.agg) {
+    hipStream_t sa = split ? s2 : s;
+    HIP_TRY(launch_fill32(ws2.at<uint32_t>(ws2.L.tickets), kMaxTickets, 0, sa));
+    uint64_t *seg = ws2.at<uint64_t>(ws2.L.seg);
+    HIP_TRY(launch_seg1(seg, nullptr, b.N, sa));
+    PacketOut o{};
+    o.stats = reinterpret_cast<uint64_t *>(b.agg_stats);
+    o.ukeys = b.agg->keys;
+    o.counts = b.agg->counts;
+    o.nnz = b.agg->nnz;
+    o.sort_a = b.agg->counts;
+    o.sort_b = b.agg->keys;
+    int rc = enqueue_packets(ws2, b.sh, b.src, b.dst, seg, 1, b.N, o, sa);
+    if (rc) return rc;
+    if (split) HIP_TRY(hipEventRecord(join, s2));
+  }
   if (b.W > 0) {
     PacketOut o{};
     o.stats = reinterpret_cast<uint64_t *>(b.out);
@@ -439,26 +468,14 @@ int enqueue_batch(const BatchArgs &b, Ws &ws, hipStream_t s) {
     int rc = enqueue_packets(ws, b.sh, b.src, b.dst, b.offsets, b.W, b.N, o, s);
     if (rc) return rc;
   }
-  if (b.agg) {
-    uint64_t *seg = ws.at<uint64_t>(ws.L.seg);
-    HIP_TRY(launch_seg1(seg, nullptr, b.N, s));
-    PacketOut o{};
-    o.stats = reinterpret_cast<uint64_t *>(b.agg_stats);
-    o.ukeys = b.agg->keys;
-    o.counts = b.agg->counts;
-    o.nnz = b.agg->nnz;
-    o.sort_a = b.agg->counts;
-    o.sort_b = b.agg->keys;
-    int rc = enqueue_packets(ws, b.sh, b.src, b.dst, seg, 1, b.N, o, s);
-    if (rc) return rc;
-  }
+  if (split) HIP_TRY(hipStreamWaitEvent(s, join, 0));
   return NS_OK;
 }
 
 int batch_checks(const uint32_t *src, const uint32_t *dst, const uint64_t *offsets, uint32_t W,
                  uint64_t N, ns_stats_t *out, ns_matrix_t *agg, ns_stats_t *agg_stats,
                  ns_batch_matrices_t *win, const ns_tuning_t *tune, void *ws, uint64_t ws_bytes,
-                 BatchArgs *b, Ws *w) {
+                 BatchArgs *b, Ws *w, Ws *w2) {
   if (N > 0 && (!src || !dst)) return NS_ERR_INVALID_ARG;
   if (W > 0 && (!offsets || !out)) return NS_ERR_INVALID_ARG;
   if (W == 0 && N > 0) return NS_ERR_INVALID_ARG;
@@ -475,8 +492,15 @@ int batch_checks(const uint32_t *src, const uint32_t *dst, const uint64_t *offse
   b->sh = Shapes{};
   int rc = resolve_tuning(tune, &b->sh);
   if (rc) return rc;
+  // the workspace holds the per-window layout, then the aggregate's layout
   rc = check_ws(ws, ws_bytes, N, W, w);
   if (rc) return rc;
+  const uint64_t first = up(w->L.total);
+  if (agg) {
+    if (ws_bytes < first) return NS_ERR_WORKSPACE;
+    rc = check_ws(static_cast<uint8_t *>(ws) + first, ws_bytes - first, N, 1, w2);
+    if (rc) return rc;
+  }
   b->src = src;
   b->dst = dst;
   b->offsets = offsets;
@@ -527,7 +551,8 @@ const char *ns_error_string(int code) {
 
 int ns_workspace_size(uint64_t max_packets, uint32_t num_windows, uint64_t *bytes) {
   if (!bytes) return NS_ERR_INVALID_ARG;
-  *bytes = plan(max_packets, num_windows).total;
+  // a batched call with an aggregate uses a second, single-window layout
+  *bytes = up(plan(max_packets, num_windows).total) + plan(max_packets, 1).total;
   return NS_OK;
 }
 
@@ -623,11 +648,12 @@ int ns_batch_stats_eager(const uint32_t *src, const uint32_t *dst, const uint64_
                          ns_batch_matrices_t *win_out, const ns_tuning_t *tune, void *ws,
                          uint64_t ws_bytes, void *stream) {
   BatchArgs b;
-  Ws w;
+  Ws w, w2;
   int rc = batch_checks(src, dst, offsets, num_windows, total_packets, out, agg_out, agg_stats,
-                        win_out, tune, ws, ws_bytes, &b, &w);
+                        win_out, tune, ws, ws_bytes, &b, &w, &w2);
   if (rc) return rc;
-  rc = enqueue_batch(b, w, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = enqueue_batch(b, w, w2, s, s, nullptr, nullptr);
   if (rc) return rc;
   if (agg_out) agg_out->packets = total_packets;
   return NS_OK;
@@ -638,9 +664,9 @@ int ns_batch_stats(const uint32_t *src, const uint32_t *dst, const uint64_t *off
                    ns_matrix_t *agg_out, ns_stats_t *agg_stats, ns_batch_matrices_t *win_out,
                    const ns_tuning_t *tune, void *ws, uint64_t ws_bytes, void *stream) {
   BatchArgs b;
-  Ws w;
+  Ws w, w2;
   int rc = batch_checks(src, dst, offsets, num_windows, total_packets, out, agg_out, agg_stats,
-                        win_out, tune, ws, ws_bytes, &b, &w);
+                        win_out, tune, ws, ws_bytes, &b, &w, &w2);
   if (rc) return rc;
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -653,10 +679,15 @@ int ns_batch_stats(const uint32_t *src, const uint32_t *dst, const uint64_t *off
   if (it != c.execs.end()) {
     exec = it->second;
   } else {
-    if (!c.capture[dev]) HIP_TRY(hipStreamCreateWithFlags(&c.capture[dev], hipStreamNonBlocking));
+    if (!c.capture[dev]) {
+      HIP_TRY(hipStreamCreateWithFlags(&c.capture[dev], hipStreamNonBlocking));
+      HIP_TRY(hipStreamCreateWithFlags(&c.capture2[dev], hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&c.fork[dev], hipEventDisableTiming));
+      HIP_TRY(hipEventCreateWithFlags(&c.join[dev], hipEventDisableTiming));
+    }
     hipStream_t cs = c.capture[dev];
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    rc = enqueue_batch(b, w, cs);
+    rc = enqueue_batch(b, w, w2, cs, c.capture2[dev], c.fork[dev], c.join[dev]);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(cs, &g);
     if (rc || e != hipSuccess) {
