@@ -48,10 +48,10 @@ Layout plan(uint64_t N, uint32_t W) {
   L.tickets = take(kMaxTickets * 4);
   L.seg = take(W1 * 8);
   L.t_sort = take((W1 + 1) * 8);
-  L.t_hist = take(W1 * 8);
-  L.t_rle = take(W1 * 8);
+  L.t_hist = take((W1 + 1) * 8);
+  L.t_rle = take((W1 + 1) * 8);
   L.t_csort = take((W1 + 1) * 8);
-  L.t_run = take(W1 * 8);
+  L.t_run = take((W1 + 1) * 8);
   L.link_off = take(W1 * 8);
   L.row_off = take(W1 * 8);
   L.col_off = take(W1 * 8);

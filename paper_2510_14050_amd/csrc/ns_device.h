@@ -113,19 +113,20 @@ __device__ __forceinline__ uint32_t find_owner(const uint64_t *off, uint32_t W, 
   return lo;
 }
 
-// Same result as lb_walk, with up to four predecessor words in flight per
-// round trip (each thread issues the loads of tiles j, j-1, j-2, j-3 together).
-__device__ __forceinline__ uint64_t lb_walk4(const uint64_t *lb, uint32_t stride, uint32_t chan,
+// Same result as lb_walk, with up to P predecessor words in flight per round
+// trip (each thread issues the loads of tiles j, j-1, ..., j-P+1 together).
+template <int P>
+__device__ __forceinline__ uint64_t lb_walkn(const uint64_t *lb, uint32_t stride, uint32_t chan,
                                              uint32_t t, uint32_t first) {
   uint64_t excl = 0;
   int64_t j = (int64_t)t - 1;
   while (j >= (int64_t)first) {
-    uint64_t v[4];
+    uint64_t v[P];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < P; ++q)
       v[q] = (j - q >= (int64_t)first) ? lb_load(lb + (uint64_t)(j - q) * stride + chan) : 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < P; ++q) {
       if (j - q < (int64_t)first) return excl;
       const uint64_t *p = lb + (uint64_t)(j - q) * stride + chan;
       while ((v[q] >> 62) == 0) {
@@ -135,7 +136,7 @@ __device__ __forceinline__ uint64_t lb_walk4(const uint64_t *lb, uint32_t stride
       excl += v[q] & kLbVal;
       if ((v[q] >> 62) == 2) return excl;
     }
-    j -= 4;
+    j -= P;
   }
   return excl;
 }

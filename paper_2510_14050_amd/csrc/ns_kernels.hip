@@ -12,6 +12,13 @@
 #include "ns_device.h"
 #include "ns_launch.h"
 
+#ifndef NS_LAYER_MAX_W
+#define NS_LAYER_MAX_W 256  // most segments for layered ticket order
+#endif
+#ifndef NS_LB_DEPTH
+#define NS_LB_DEPTH 4  // look-back words in flight per thread and round trip
+#endif
+
 namespace ns {
 
 __device__ int g_status;  // bit 0: subtraction below zero; bit 1: a hash table is full
@@ -45,13 +52,16 @@ __global__ __launch_bounds__(1024) void k_tiles(const uint64_t *seg_off, uint32_
                                                 uint64_t *oa, uint32_t tb, uint64_t *ob,
                                                 uint32_t tc, uint64_t *oc) {
   __shared__ uint64_t s_tmp[16];
-  uint64_t ca = 0, cb = 0, cc = 0;
+  __shared__ uint64_t s_max[16];
+  uint64_t ca = 0, cb = 0, cc = 0, mx = 0;
   for (uint32_t base = 0; base < W; base += 1024) {
     const uint32_t w = base + threadIdx.x;
     const uint64_t len = (w < W) ? seg_off[w + 1] - seg_off[w] : 0;
     uint64_t tot;
     if (oa) {
-      const uint64_t x = block_excl_scan<1024>((len + ta - 1) / ta, s_tmp, &tot);
+      const uint64_t nt = (len + ta - 1) / ta;
+      mx = mx > nt ? mx : nt;
+      const uint64_t x = block_excl_scan<1024>(nt, s_tmp, &tot);
       if (w < W) oa[w] = ca + x;
       ca += tot;
     }
@@ -66,8 +76,19 @@ __global__ __launch_bounds__(1024) void k_tiles(const uint64_t *seg_off, uint32_
       cc += tot;
     }
   }
+  mx = wave_max(mx);
+  if ((threadIdx.x & (kWave - 1)) == 0) s_max[threadIdx.x / kWave] = mx;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    if (oa) oa[W] = ca;
+    for (int q = 0; q < 16; ++q) mx = mx > s_max[q] ? mx : s_max[q];
+    if (oa) {
+      oa[W] = ca;
+      // layered ticket order (see pass_ticket) for a few segments of similar
+      // length: at most a quarter of the tickets go to absent tiles. With many
+      // segments, tile order keeps each segment's writes close in time, which
+      // the memory-side cache merges into whole lines; 0 selects tile order.
+      oa[W + 1] = (W > 1 && W <= NS_LAYER_MAX_W && (uint64_t)W * mx <= ca + ca / 4) ? mx : 0;
+    }
     if (ob) ob[W] = cb;
     if (oc) oc[W] = cc;
   }
@@ -157,6 +178,56 @@ __global__ __launch_bounds__(256) void k_hist_scan(const uint32_t *hist, uint32_
 // segment. Keys are scattered into LDS in digit order and written out from
 // there, so consecutive threads write consecutive addresses within a digit.
 // ---------------------------------------------------------------------------
+// Next tile of a radix pass. With several segments of similar length, tickets
+// go layer by layer: ticket k is tile k / W of segment k % W (tickets of absent
+// tiles are skipped), so a tile's predecessor in its segment holds a ticket W
+// smaller and has usually finished. Otherwise tickets follow tile order. Either
+// way every predecessor holds a smaller ticket, so look-back waits always end.
+// Returns ~0u when the pass is exhausted; *seg receives the tile's segment.
+__device__ __forceinline__ uint32_t pass_ticket(const PassArgs &a, uint64_t layers,
+                                                uint64_t tickets, uint32_t *seg) {
+  for (;;) {
+    const uint64_t k = atomicAdd(a.ticket, 1u);
+    if (k >= tickets) return 0xFFFFFFFFu;
+    if (!layers) {
+      *seg = find_owner(a.tile_off, a.W, k);
+      return (uint32_t)k;
+    }
+    const uint32_t w = (uint32_t)(k % a.W);
+    const uint64_t j = k / a.W;
+    if (a.tile_off[w] + j < a.tile_off[w + 1]) {
+      *seg = w;
+      return (uint32_t)(a.tile_off[w] + j);
+    }
+  }
+}
+
+// Load one tile wave-striped: item k of lane l of wave v is key
+// start + v*64*ITEMS + k*64 + l. Missing keys get digit kBins.
+template <int ITEMS, bool PACKETS>
+__device__ __forceinline__ void pass_load(const PassArgs &a, uint64_t start, uint32_t n,
+                                          uint32_t wbase, int lane, uint32_t full,
+                                          uint64_t (&key)[ITEMS]) {
+  if (n == full) {  // full tile: unpredicated loads
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint64_t i = start + wbase + k * kWave + lane;
+      key[k] = PACKETS ? pack_key(a.src[i], a.dst[i]) : a.in[i];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t li = wbase + k * kWave + lane;
+      uint64_t x = 0;
+      if (li < n) {
+        if (PACKETS) x = pack_key(a.src[start + li], a.dst[start + li]);
+        else x = a.in[start + li];
+      }
+      key[k] = x;
+    }
+  }
+}
+
 template <int BLOCK, int ITEMS, bool PACKETS>
 __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
   constexpr int TILE = BLOCK * ITEMS;
@@ -167,47 +238,46 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
   __shared__ uint32_t s_tot[kBins];
   __shared__ uint32_t s_lstart[kBins];
   __shared__ uint64_t s_gbase[kBins];
-  __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_tile, s_seg;
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  const uint64_t total = a.tile_off[a.W];
   const uint32_t shift = a.shift;
+  const uint64_t layers = a.tile_off[a.W + 1];
+  const uint64_t tickets = layers ? (uint64_t)a.W * layers : a.tile_off[a.W];
+  const uint32_t wbase = wv * (kWave * ITEMS);
+  // Several segments: the keys of the next tile are requested before this
+  // tile's look-back, so their memory latency overlaps the wait. One segment:
+  // the next ticket is drawn only after the scatter, since a tile held while
+  // another one finishes would delay its own published counts and lengthen
+  // every later tile's look-back.
+  const bool pipe = a.W > 1;
 
-  for (;;) {
-    if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
-    for (int i = tid; i < NW * kBins; i += BLOCK) (&s_wcnt[0][0])[i] = 0;
-    __syncthreads();
-    const uint32_t t = s_tile;
-    if (t >= total) break;
-    const uint32_t w = find_owner(a.tile_off, a.W, t);
-    const uint32_t first = (uint32_t)a.tile_off[w];
-    const uint64_t seg_lo = a.seg_off[w];
+  for (int i = tid; i < NW * kBins; i += BLOCK) (&s_wcnt[0][0])[i] = 0;
+  if (tid == 0) {
+    uint32_t w = 0;
+    s_tile = pass_ticket(a, layers, tickets, &w);
+    s_seg = w;
+  }
+  __syncthreads();
+  uint32_t t = s_tile, w = s_seg;
+  uint64_t seg_lo = 0;
+  uint32_t first = 0, n = 0;
+  uint64_t key[ITEMS];
+  if (t != 0xFFFFFFFFu) {
+    first = (uint32_t)a.tile_off[w];
+    seg_lo = a.seg_off[w];
     const uint64_t start = seg_lo + (uint64_t)(t - first) * TILE;
-    const uint32_t n = (uint32_t)min((uint64_t)TILE, a.seg_off[w + 1] - start);
+    n = (uint32_t)min((uint64_t)TILE, a.seg_off[w + 1] - start);
+    pass_load<ITEMS, PACKETS>(a, start, n, wbase, lane, TILE, key);
+  }
 
-    uint64_t key[ITEMS];
+  while (t != 0xFFFFFFFFu) {
     uint32_t dig[ITEMS];
     uint32_t rank[ITEMS];
-    const uint32_t wbase = wv * (kWave * ITEMS);
-    if (n == TILE) {  // full tile: unpredicated loads
 #pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        const uint64_t i = start + wbase + k * kWave + lane;
-        key[k] = PACKETS ? pack_key(a.src[i], a.dst[i]) : a.in[i];
-        dig[k] = (uint32_t)(key[k] >> shift) & 255u;
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t li = wbase + k * kWave + lane;
-        uint64_t x = 0;
-        if (li < n) {
-          if (PACKETS) x = pack_key(a.src[start + li], a.dst[start + li]);
-          else x = a.in[start + li];
-        }
-        key[k] = x;
-        dig[k] = (li < n) ? (uint32_t)(x >> shift) & 255u : kBins;
-      }
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t li = wbase + k * kWave + lane;
+      dig[k] = li < n ? (uint32_t)(key[k] >> shift) & 255u : kBins;
     }
     // stable rank within the wave, in (k, lane) order = original order. The
     // peer mask is built on 32-bit halves: for each digit bit, the ballot m is
@@ -245,8 +315,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
       }
       s_tot[tid] = sum;
       // publish this tile's digit counts as early as possible
-      uint64_t *row = a.lb + (uint64_t)t * kBins;
-      lb_store(row + tid, (t == first ? kLbInc : kLbAgg) | sum);
+      lb_store(a.lb + (uint64_t)t * kBins + tid, (t == first ? kLbInc : kLbAgg) | sum);
     }
     __syncthreads();
     if (tid < kWave) {  // exclusive scan of the 256 digit totals, 4 per lane
@@ -259,20 +328,42 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
       s_lstart[tid * 4 + 2] = x + v0 + v1;
       s_lstart[tid * 4 + 3] = x + v0 + v1 + v2;
     }
-    if (tid < kBins) {
-      uint64_t excl = 0;
-      if (t != first) {
-        excl = lb_walk4(a.lb, kBins, tid, t, first);
-        lb_store(a.lb + (uint64_t)t * kBins + tid, kLbInc | (excl + s_tot[tid]));
-      }
-      s_gbase[tid] = seg_lo + a.base[(uint64_t)w * a.base_stride + tid] + excl;
-      a.lb_next[(uint64_t)t * kBins + tid] = 0;
-    }
     __syncthreads();
+    // local counting sort of the tile into LDS; the key registers are free after
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const uint32_t d = dig[k];
       if (d < kBins) s_keys[s_lstart[d] + s_wcnt[wv][d] + rank[k]] = key[k];
+    }
+    if (pipe && tid == 0) {
+      uint32_t nw = 0;
+      s_tile = pass_ticket(a, layers, tickets, &nw);
+      s_seg = nw;
+    }
+    __syncthreads();
+    for (int i = tid; i < NW * kBins; i += BLOCK) (&s_wcnt[0][0])[i] = 0;
+    uint32_t t2 = 0xFFFFFFFFu, w2 = 0;
+    uint64_t seg_lo2 = 0;
+    uint32_t first2 = 0, n2 = 0;
+    if (pipe) {
+      t2 = s_tile;
+      w2 = s_seg;
+      if (t2 != 0xFFFFFFFFu) {  // prefetch the next tile
+        first2 = (uint32_t)a.tile_off[w2];
+        seg_lo2 = a.seg_off[w2];
+        const uint64_t start2 = seg_lo2 + (uint64_t)(t2 - first2) * TILE;
+        n2 = (uint32_t)min((uint64_t)TILE, a.seg_off[w2 + 1] - start2);
+        pass_load<ITEMS, PACKETS>(a, start2, n2, wbase, lane, TILE, key);
+      }
+    }
+    if (tid < kBins) {
+      uint64_t excl = 0;
+      if (t != first) {
+        excl = lb_walkn<NS_LB_DEPTH>(a.lb, kBins, tid, t, first);
+        lb_store(a.lb + (uint64_t)t * kBins + tid, kLbInc | (excl + s_tot[tid]));
+      }
+      s_gbase[tid] = seg_lo + a.base[(uint64_t)w * a.base_stride + tid] + excl;
+      a.lb_next[(uint64_t)t * kBins + tid] = 0;
     }
     __syncthreads();
     for (uint32_t i = tid; i < n; i += BLOCK) {
@@ -280,7 +371,28 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
       const uint32_t d = (uint32_t)(x >> shift) & 255u;
       a.out[s_gbase[d] + (i - s_lstart[d])] = x;
     }
+    if (!pipe && tid == 0) {
+      uint32_t nw = 0;
+      s_tile = pass_ticket(a, layers, tickets, &nw);
+      s_seg = nw;
+    }
     __syncthreads();
+    if (!pipe) {
+      t2 = s_tile;
+      w2 = s_seg;
+      if (t2 != 0xFFFFFFFFu) {
+        first2 = (uint32_t)a.tile_off[w2];
+        seg_lo2 = a.seg_off[w2];
+        const uint64_t start2 = seg_lo2 + (uint64_t)(t2 - first2) * TILE;
+        n2 = (uint32_t)min((uint64_t)TILE, a.seg_off[w2 + 1] - start2);
+        pass_load<ITEMS, PACKETS>(a, start2, n2, wbase, lane, TILE, key);
+      }
+    }
+    t = t2;
+    w = w2;
+    first = first2;
+    seg_lo = seg_lo2;
+    n = n2;
   }
 }
 

@@ -30,7 +30,9 @@ hipError_t launch_fill64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_fill32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 // seg[0] = 0, seg[1] = min(*n_dev, n) if n_dev else n
 hipError_t launch_seg1(uint64_t *seg, const uint64_t *n_dev, uint64_t n, hipStream_t s);
-// per-segment tile prefix for up to three tile sizes (null outputs skipped)
+// per-segment tile prefix for up to three tile sizes (null outputs skipped);
+// oa[W+1] receives the layer count for layered ticket order, or 0 (oa needs
+// W+2 entries)
 hipError_t launch_tiles(const uint64_t *seg_off, uint32_t W, uint32_t ta, uint64_t *oa,
                         uint32_t tb, uint64_t *ob, uint32_t tc, uint64_t *oc, hipStream_t s);
 
@@ -47,7 +49,7 @@ struct PassArgs {
   const uint64_t *in;        // u64 input otherwise
   uint64_t *out;
   const uint64_t *seg_off;   // [W+1]
-  const uint64_t *tile_off;  // [W+1] tiles of this sort's tile size
+  const uint64_t *tile_off;  // [W+2] tile prefix of this sort's tile size, [W+1] = layers
   uint32_t W;
   uint32_t shift;            // digit = (key >> shift) & 255
   const uint32_t *base;      // bucket starts of this digit: base[w*base_stride + bin]
