@@ -82,12 +82,17 @@ typedef struct {
  *   sort_block   workgroup size of the radix passes (256 or 512)
  *   sort_items   keys per thread in a radix pass (8 or 16): tile = block*items
  *   digit_bits   radix digit width (8)
- *   scan_items   positions per thread in the run-length / run-reduce passes (4 or 8) */
+ *   scan_items   positions per thread in the run-length / run-reduce passes (4, 8 or 16)
+ *   chunked_min  a single segment (one window, or the aggregate of all windows)
+ *                of at least this many keys is sorted by chunked passes (count,
+ *                scan, scatter) rather than passes with look-back; 0 = 2^24,
+ *                UINT64_MAX = never. Results are identical either way. */
 typedef struct {
   uint32_t sort_block;
   uint32_t sort_items;
   uint32_t digit_bits;
   uint32_t scan_items;
+  uint64_t chunked_min;
 } ns_tuning_t;
 
 /* Per-window matrices of a batch, laid out by packet offset: window w's
@@ -204,7 +209,9 @@ int ns_release_graphs(void);
  * launches (host *launches). Kinds: 0 fill, 1 tile setup, 2 digit histogram,
  * 3 histogram scan, 4 first radix pass (packs keys), 5 other key radix passes,
  * 6 column radix passes, 7 run-length encoding, 8 run reduction,
- * 9 segment maxima, 10 finalize, 11 merge. ns_timing_reset destroys the
+ * 9 segment maxima, 10 finalize, 11 merge, 12 digit counts and scans of the
+ * chunked passes, 13 first radix pass (chunked), 14 other key radix passes
+ * (chunked), 15 column radix passes (chunked). ns_timing_reset destroys the
  * recorded events. */
 int ns_timing_enable(int on);
 int ns_timing_reset(void);

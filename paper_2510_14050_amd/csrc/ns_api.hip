@@ -19,6 +19,12 @@ namespace {
 
 constexpr uint64_t kAlign = 256;
 constexpr int kMaxTickets = 64;
+// A single segment of at least this many keys is sorted by chunked passes
+// (reduce, scan, scatter) instead of passes with look-back.
+#ifndef NS_CHUNKED_MIN
+#define NS_CHUNKED_MIN (1ull << 24)
+#endif
+constexpr uint64_t kChunkedMin = NS_CHUNKED_MIN;
 constexpr uint64_t kMaxPackets32 = 0xFFFFFFFFull;  // packets per window / matrix < 2^32
 constexpr int kMinSortTile = 256 * 8;
 constexpr int kMinScanTile = 256 * 4;
@@ -32,6 +38,7 @@ struct Layout {
   uint64_t link_off, row_off, col_off, seg_base;
   uint64_t hist, base, chist, cbase;
   uint64_t lb0, lb1, lbs;
+  uint64_t ccount, cprefix;
   uint64_t KA, KB, HA, HB;
   uint64_t total;
   uint64_t sort_tiles, scan_tiles;
@@ -63,6 +70,8 @@ Layout plan(uint64_t N, uint32_t W) {
   L.lb0 = take(L.sort_tiles * kBins * 8);
   L.lb1 = take(L.sort_tiles * kBins * 8);
   L.lbs = take(L.scan_tiles * 2 * 8);
+  L.ccount = take((uint64_t)kChunks * kBins * 4);
+  L.cprefix = take((uint64_t)(kChunks + 1) * kBins * 8);  // + digit totals
   L.KA = take((N + 1) * 8);
   L.KB = take((N + 1) * 8);
   L.HA = take((N + 2) * 8);
@@ -89,7 +98,8 @@ struct Ws {
 // Optional per-kernel timing: HIP events recorded on the launching stream
 // around every launch of the eager paths (never inside a captured graph).
 enum Kind { K_FILL, K_TILES, K_HIST, K_HSCAN, K_PASS0, K_PASS, K_CPASS, K_RLE, K_RUNS, K_SEGMAX,
-            K_FINAL, K_MERGE, K_COUNT };
+            K_FINAL, K_MERGE, K_CHUNK_COUNT, K_PASS0_CHUNKED, K_PASS_CHUNKED, K_CPASS_CHUNKED,
+            K_COUNT };
 
 struct Profiler {
   std::mutex mu;
@@ -133,11 +143,16 @@ int check_ws(void *ws, uint64_t ws_bytes, uint64_t N, uint32_t W, Ws *out) {
 struct Shapes {
   SortShape sort;
   ScanShape scan;
+  uint64_t chunked_min = kChunkedMin;
+  // chunked passes: the largest tile measured fastest (fewest tiles per chunk
+  // boundary, most keys per digit run)
+  SortShape chunk = {512, 16};
 };
 
 int resolve_tuning(const ns_tuning_t *t, Shapes *sh) {
   sh->sort = {256, 16};
   sh->scan = {8};
+  sh->chunked_min = kChunkedMin;
   if (!t) return NS_OK;
   if (t->digit_bits && t->digit_bits != 8) return NS_ERR_INVALID_ARG;
   if (t->sort_block) {
@@ -149,9 +164,10 @@ int resolve_tuning(const ns_tuning_t *t, Shapes *sh) {
     sh->sort.items = (int)t->sort_items;
   }
   if (t->scan_items) {
-    if (t->scan_items != 4 && t->scan_items != 8) return NS_ERR_INVALID_ARG;
+    if (t->scan_items != 4 && t->scan_items != 8 && t->scan_items != 16) return NS_ERR_INVALID_ARG;
     sh->scan.items = (int)t->scan_items;
   }
+  if (t->chunked_min) sh->chunked_min = t->chunked_min;
   return NS_OK;
 }
 
@@ -162,30 +178,44 @@ int resolve_tuning(const ns_tuning_t *t, Shapes *sh) {
 // On return the sorted items are in `tmp` (4 passes: in -> tmp -> in -> tmp -> in
 // ... ends in items_in).
 int enqueue_columns(Ws &ws, const Shapes &sh, uint64_t *items, uint64_t *tmp,
-                    const uint64_t *link_off, uint32_t W, uint64_t max_items,
-                    const uint32_t *chist, uint64_t *stats, hipStream_t s) {
+                    const uint64_t *link_off, uint32_t W, uint64_t max_items, uint64_t *stats,
+                    hipStream_t s) {
   const Layout &L = ws.L;
   uint64_t *t_csort = ws.at<uint64_t>(L.t_csort), *t_run = ws.at<uint64_t>(L.t_run);
-  uint32_t *cbase = ws.at<uint32_t>(L.cbase);
-  HIP_TRY(timed(K_TILES, s, [&] { return launch_tiles(link_off, W, sh.sort.tile(), t_csort, sh.scan.tile(), t_run, 1, nullptr, s); }));
-  HIP_TRY(timed(K_HSCAN, s, [&] { return launch_hist_scan(chist, cbase, (uint64_t)W * kColDigits, s); }));
+  uint32_t *chist = ws.at<uint32_t>(L.chist), *cbase = ws.at<uint32_t>(L.cbase);
+  const bool chunked = W == 1 && max_items >= sh.chunked_min;
+  uint64_t *t_chist = ws.at<uint64_t>(L.t_hist);  // free again once the key histograms are done
+  HIP_TRY(timed(K_TILES, s, [&] { return launch_tiles(link_off, W, sh.sort.tile(), t_csort, sh.scan.tile(), t_run, kHistTile, t_chist, s); }));
+  if (!chunked) {
+    const uint64_t hist_tiles = max_items / kHistTile + W + 1;
+    HIP_TRY(launch_fill32(chist, (uint64_t)W * kColDigits * kBins, 0, s));
+    HIP_TRY(timed(K_HIST, s, [&] { return launch_hist_items(items, link_off, t_chist, W, hist_tiles, chist, s); }));
+    HIP_TRY(timed(K_HSCAN, s, [&] { return launch_hist_scan(chist, cbase, (uint64_t)W * kColDigits, s); }));
+  }
   const uint64_t sort_tiles = max_items / sh.sort.tile() + W + 1;
   uint64_t *lb[2] = {ws.at<uint64_t>(L.lb0), ws.at<uint64_t>(L.lb1)};
   uint64_t *buf[2] = {items, tmp};
-  HIP_TRY(timed(K_CPASS, s, [&] {
+  HIP_TRY(timed(chunked ? K_CPASS_CHUNKED : K_CPASS, s, [&] {
     for (int q = 0; q < kColDigits; ++q) {
       PassArgs a{};
       a.in = buf[q & 1];
       a.out = buf[(q + 1) & 1];
+      a.shift = 32 + 8 * q;
+      a.ticket = ws.ticket();
+      if (chunked) {
+        ChunkArgs c{link_off, 0, ws.at<uint32_t>(L.ccount), ws.at<uint64_t>(L.cprefix),
+                    ws.at<uint64_t>(L.cprefix) + (uint64_t)kChunks * kBins};
+        const hipError_t e = launch_pass_chunked(sh.chunk, a, c, max_items, K_CHUNK_COUNT, s);
+        if (e != hipSuccess) return e;
+        continue;
+      }
       a.seg_off = link_off;
       a.tile_off = t_csort;
       a.W = W;
-      a.shift = 32 + 8 * q;
       a.base = cbase + q * kBins;
       a.base_stride = kColDigits * kBins;
       a.lb = lb[q & 1];
       a.lb_next = lb[(q + 1) & 1];
-      a.ticket = ws.ticket();
       const hipError_t e = launch_pass(sh.sort, a, sort_tiles, s);
       if (e != hipSuccess) return e;
     }
@@ -237,7 +267,6 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
   uint64_t *t_sort = ws.at<uint64_t>(L.t_sort), *t_hist = ws.at<uint64_t>(L.t_hist),
            *t_rle = ws.at<uint64_t>(L.t_rle);
   uint32_t *hist = ws.at<uint32_t>(L.hist), *base = ws.at<uint32_t>(L.base);
-  uint32_t *chist = ws.at<uint32_t>(L.chist);
   uint64_t *link_off = ws.at<uint64_t>(L.link_off);
   uint64_t *row_off = ws.at<uint64_t>(L.row_off);
   uint64_t *lb[2] = {ws.at<uint64_t>(L.lb0), ws.at<uint64_t>(L.lb1)};
@@ -245,13 +274,15 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
   const uint64_t rle_tiles = N / sh.scan.tile() + W + 1;
   const uint64_t hist_tiles = N / kHistTile + W + 1;
   const bool want_stats = o.stats != nullptr;
+  // one large segment: chunked passes, which need neither the digit
+  // histograms nor the look-back words (the column passes follow suit)
+  const bool chunked = W == 1 && N >= sh.chunked_min;
 
-  HIP_TRY(launch_fill32(hist, (uint64_t)W * kKeyDigits * kBins, 0, s));
+  if (!chunked) HIP_TRY(launch_fill32(hist, (uint64_t)W * kKeyDigits * kBins, 0, s));
   if (want_stats) {
-    HIP_TRY(launch_fill32(chist, (uint64_t)W * kColDigits * kBins, 0, s));
     HIP_TRY(launch_fill64(o.stats, (uint64_t)W * 8, 0, s));
   }
-  HIP_TRY(launch_fill64(lb[0], sort_tiles * kBins, 0, s));
+  if (!chunked) HIP_TRY(launch_fill64(lb[0], sort_tiles * kBins, 0, s));
   HIP_TRY(launch_fill64(link_off, (uint64_t)W + 1, 0, s));
   HIP_TRY(launch_fill64(row_off, (uint64_t)W + 1, 0, s));
   if (o.nnz) HIP_TRY(launch_fill64(o.nnz, 1, 0, s));
@@ -261,8 +292,10 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
   }
   HIP_TRY(launch_tiles(seg_off, W, sh.sort.tile(), t_sort, kHistTile, t_hist, sh.scan.tile(),
                        t_rle, s));
-  HIP_TRY(timed(K_HIST, s, [&] { return launch_hist_packets(src, dst, seg_off, t_hist, W, hist_tiles, hist, s); }));
-  HIP_TRY(timed(K_HSCAN, s, [&] { return launch_hist_scan(hist, base, (uint64_t)W * kKeyDigits, s); }));
+  if (!chunked) {
+    HIP_TRY(timed(K_HIST, s, [&] { return launch_hist_packets(src, dst, seg_off, t_hist, W, hist_tiles, hist, s); }));
+    HIP_TRY(timed(K_HSCAN, s, [&] { return launch_hist_scan(hist, base, (uint64_t)W * kKeyDigits, s); }));
+  }
   // 8 stable byte passes, least significant first; pass p writes buf[p & 1]
   uint64_t *buf[2] = {o.sort_a, o.sort_b};
   auto pass = [&](int p) {
@@ -274,19 +307,24 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
       a.in = buf[(p - 1) & 1];
     }
     a.out = buf[p & 1];
+    a.shift = 8 * p;
+    a.ticket = ws.ticket();
+    if (chunked) {
+      ChunkArgs c{seg_off, 0, ws.at<uint32_t>(L.ccount), ws.at<uint64_t>(L.cprefix),
+                  ws.at<uint64_t>(L.cprefix) + (uint64_t)kChunks * kBins};
+      return launch_pass_chunked(sh.chunk, a, c, N, K_CHUNK_COUNT, s);
+    }
     a.seg_off = seg_off;
     a.tile_off = t_sort;
     a.W = W;
-    a.shift = 8 * p;
     a.base = base + p * kBins;
     a.base_stride = kKeyDigits * kBins;
     a.lb = lb[p & 1];
     a.lb_next = lb[(p + 1) & 1];
-    a.ticket = ws.ticket();
     return launch_pass(sh.sort, a, sort_tiles, s);
   };
-  HIP_TRY(timed(K_PASS0, s, [&] { return pass(0); }));
-  HIP_TRY(timed(K_PASS, s, [&] {
+  HIP_TRY(timed(chunked ? K_PASS0_CHUNKED : K_PASS0, s, [&] { return pass(0); }));
+  HIP_TRY(timed(chunked ? K_PASS_CHUNKED : K_PASS, s, [&] {
     for (int p = 1; p < kKeyDigits; ++p) {
       const hipError_t e = pass(p);
       if (e != hipSuccess) return e;
@@ -319,7 +357,6 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
   r.seg_base = ws.at<uint64_t>(L.seg_base);
   r.rpos = rpos;
   r.rlink = rlink;
-  r.col_hist = want_stats ? chist : nullptr;
   r.link_off = link_off;
   r.row_off = row_off;
   r.nnz_out = o.nnz;
@@ -331,7 +368,7 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
   HIP_TRY(timed(K_SEGMAX, s, [&] { return launch_segmax(rpos, rlink, row_off, W, N, o.stats, 4, 5, s); }));
   // columns: items are sorted in place (ping-pong with the other sort buffer)
   uint64_t *tmp = (items == ws.at<uint64_t>(L.KA)) ? ws.at<uint64_t>(L.KB) : ws.at<uint64_t>(L.KA);
-  int rc = enqueue_columns(ws, sh, items, tmp, link_off, W, N, chist, o.stats, s);
+  int rc = enqueue_columns(ws, sh, items, tmp, link_off, W, N, o.stats, s);
   if (rc) return rc;
   HIP_TRY(timed(K_FINAL, s, [&] { return launch_finalize(seg_off, link_off, row_off, ws.at<uint64_t>(L.col_off), W, o.stats, s); }));
   return NS_OK;
@@ -346,14 +383,12 @@ int enqueue_matrix_stats(Ws &ws, const Shapes &sh, const ns_matrix_t *m, uint64_
   uint64_t *t_run = ws.at<uint64_t>(L.t_run);
   uint64_t *link_off = ws.at<uint64_t>(L.link_off);
   uint64_t *row_off = ws.at<uint64_t>(L.row_off);
-  uint32_t *chist = ws.at<uint32_t>(L.chist);
   uint64_t *items = ws.at<uint64_t>(L.KA), *tmp = ws.at<uint64_t>(L.KB);
   uint64_t *hpos = ws.at<uint64_t>(L.HA), *hval = ws.at<uint64_t>(L.HB);
   uint64_t *lbs = ws.at<uint64_t>(L.lbs);
   const uint64_t run_tiles = cap / sh.scan.tile() + 2;
 
   HIP_TRY(launch_fill64(stats, 8, 0, s));
-  HIP_TRY(launch_fill32(chist, kColDigits * kBins, 0, s));
   HIP_TRY(launch_fill64(ws.at<uint64_t>(L.lb0), (cap / sh.sort.tile() + 2) * kBins, 0, s));
   HIP_TRY(launch_fill64(lbs, run_tiles * 2, 0, s));
   HIP_TRY(launch_fill64(row_off, 2, 0, s));
@@ -372,7 +407,6 @@ int enqueue_matrix_stats(Ws &ws, const Shapes &sh, const ns_matrix_t *m, uint64_
   r.hval = hval;
   r.head_off = row_off;
   r.items = items;
-  r.col_hist = chist;
   r.lb = lbs;
   r.ticket = ws.ticket();
   HIP_TRY(timed(K_RUNS, s, [&] { return launch_runs(sh.scan, 0, r, run_tiles, s); }));
@@ -380,7 +414,7 @@ int enqueue_matrix_stats(Ws &ws, const Shapes &sh, const ns_matrix_t *m, uint64_
   HIP_TRY(timed(K_SEGMAX, s, [&] { return launch_segmax(hpos, hval, row_off, 1, cap, stats, 5, 4, s); }));
   // valid packets = value sentinel, read before the column pass reuses hpos/hval
   HIP_TRY(timed(K_FINAL, s, [&] { return launch_finalize_matrix(hval, row_off, nullptr, m->nnz, stats, s); }));
-  int rc = enqueue_columns(ws, sh, items, tmp, link_off, 1, cap, chist, stats, s);
+  int rc = enqueue_columns(ws, sh, items, tmp, link_off, 1, cap, stats, s);
   if (rc) return rc;
   HIP_TRY(timed(K_FINAL, s, [&] { return launch_finalize_matrix(nullptr, nullptr, ws.at<uint64_t>(L.col_off), nullptr, stats, s); }));
   return NS_OK;
@@ -515,7 +549,7 @@ int batch_checks(const uint32_t *src, const uint32_t *dst, const uint64_t *offse
 
 std::string batch_key(int dev, const BatchArgs &b, void *ws, uint64_t ws_bytes) {
   char buf[512];
-  snprintf(buf, sizeof buf, "%d|%p|%p|%p|%u|%llu|%p|%p|%p|%p|%llu|%p|%p|%p|%p|%p|%llu|%d,%d,%d|%p|%llu",
+  snprintf(buf, sizeof buf, "%d|%p|%p|%p|%u|%llu|%p|%p|%p|%p|%llu|%p|%p|%p|%p|%p|%llu|%d,%d,%d,%llu|%p|%llu",
            dev, (const void *)b.src, (const void *)b.dst, (const void *)b.offsets, b.W,
            (unsigned long long)b.N, (void *)b.out, b.agg ? (void *)b.agg->keys : nullptr,
            b.agg ? (void *)b.agg->counts : nullptr, b.agg ? (void *)b.agg->nnz : nullptr,
@@ -523,7 +557,7 @@ std::string batch_key(int dev, const BatchArgs &b, void *ws, uint64_t ws_bytes) 
            b.win ? (void *)b.win->keys : nullptr, b.win ? (void *)b.win->counts : nullptr,
            b.win ? (void *)b.win->nnz : nullptr, (void *)nullptr,
            (unsigned long long)(b.win ? b.win->capacity : 0), b.sh.sort.block, b.sh.sort.items,
-           b.sh.scan.items, ws, (unsigned long long)ws_bytes);
+           b.sh.scan.items, (unsigned long long)b.sh.chunked_min, ws, (unsigned long long)ws_bytes);
   return std::string(buf);
 }
 

@@ -15,6 +15,9 @@
 #ifndef NS_LAYER_MAX_W
 #define NS_LAYER_MAX_W 256  // most segments for layered ticket order
 #endif
+#ifndef NS_CHUNKS_PER_CU
+#define NS_CHUNKS_PER_CU 2  // chunks of a large single-segment pass per CU
+#endif
 #ifndef NS_LB_DEPTH
 #define NS_LB_DEPTH 4  // look-back words in flight per thread and round trip
 #endif
@@ -96,54 +99,86 @@ __global__ __launch_bounds__(1024) void k_tiles(const uint64_t *seg_off, uint32_
 
 // ---------------------------------------------------------------------------
 // Radix sort, step 1: byte-digit histograms of every key, per segment.
-// Digit p of key src<<32|dst is bits [8p, 8p+8): p<4 come from dst, p>=4 from
-// src. LDS counters per workgroup, flushed with one atomic per non-zero bin.
+// Packets: digit p of key src<<32|dst is bits [8p, 8p+8): p<4 come from dst,
+// p>=4 from src (8 digits). Column items dst<<32|count: the 4 digits of dst.
+// Each workgroup takes a contiguous range of tiles and counts into LDS; the
+// counters go to the segment's global histogram (one atomic per non-zero bin)
+// only when the range crosses into the next segment and at its end. Four
+// interleaved copies of the counters (chosen by lane) spread the updates of a
+// hot digit, which heavy-tailed traffic produces in every wave, over four
+// addresses in different banks.
 // ---------------------------------------------------------------------------
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_hist_packets(const uint32_t *__restrict__ src,
-                                                        const uint32_t *__restrict__ dst,
-                                                        const uint64_t *seg_off,
-                                                        const uint64_t *tile_off, uint32_t W,
-                                                        uint32_t *hist) {
-  __shared__ uint32_t s_h[kKeyDigits * kBins];
+template <int BLOCK, bool PACKETS>
+__global__ __launch_bounds__(BLOCK) void k_hist(const uint32_t *__restrict__ src,
+                                                const uint32_t *__restrict__ dst,
+                                                const uint64_t *__restrict__ items,
+                                                const uint64_t *seg_off, const uint64_t *tile_off,
+                                                uint32_t W, uint32_t *hist) {
+  constexpr int C = 4;
+  constexpr int ND = PACKETS ? kKeyDigits : kColDigits;
+  constexpr int NC = ND * kBins;
+  __shared__ uint32_t s_h[NC * C];
   const uint64_t total = tile_off[W];
-  for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
-    for (int i = threadIdx.x; i < kKeyDigits * kBins; i += BLOCK) s_h[i] = 0;
-    __syncthreads();
+  const uint64_t per = (total + gridDim.x - 1) / gridDim.x;
+  const uint64_t t0 = (uint64_t)blockIdx.x * per, t1 = min(total, t0 + per);
+  const uint32_t cp = threadIdx.x & (C - 1);
+  for (int i = threadIdx.x; i < NC * C; i += BLOCK) s_h[i] = 0;
+  __syncthreads();
+  auto flush = [&](uint32_t w) {
+    uint32_t *g = hist + (uint64_t)w * NC;
+    for (int i = threadIdx.x; i < NC; i += BLOCK) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        c += s_h[i * C + k];
+        s_h[i * C + k] = 0;
+      }
+      if (c) atomicAdd(&g[i], c);
+    }
+  };
+  auto count32 = [&](int d0, uint32_t v) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) atomicAdd(&s_h[((d0 + q) * kBins + ((v >> (8 * q)) & 255)) * C + cp], 1u);
+  };
+  uint32_t cur = t0 < t1 ? find_owner(tile_off, W, t0) : 0;
+  for (uint64_t t = t0; t < t1; ++t) {
     const uint32_t w = find_owner(tile_off, W, t);
+    if (w != cur) {  // uniform: every thread sees the same tile
+      __syncthreads();
+      flush(cur);
+      __syncthreads();
+      cur = w;
+    }
     const uint64_t start = seg_off[w] + (t - tile_off[w]) * (uint64_t)kHistTile;
     const uint64_t end = min(start + (uint64_t)kHistTile, seg_off[w + 1]);
-    constexpr int R = 8;  // packets per thread per round, loads issued together
+    constexpr int R = 8;  // keys per thread per round, loads issued together
     for (uint64_t i0 = start + threadIdx.x; i0 < end; i0 += (uint64_t)R * BLOCK) {
-      uint32_t sv[R], dv[R];
+      uint32_t lo[R], hi[R];
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         const uint64_t i = i0 + (uint64_t)k * BLOCK;
-        sv[k] = i < end ? src[i] : 0;
-        dv[k] = i < end ? dst[i] : 0;
+        if (PACKETS) {
+          hi[k] = i < end ? src[i] : 0;
+          lo[k] = i < end ? dst[i] : 0;
+        } else {
+          hi[k] = i < end ? (uint32_t)(items[i] >> 32) : 0;
+          lo[k] = 0;
+        }
       }
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         if (i0 + (uint64_t)k * BLOCK >= end) break;
-        const uint32_t d = dv[k], s = sv[k];
-        atomicAdd(&s_h[0 * kBins + (d & 255)], 1u);
-        atomicAdd(&s_h[1 * kBins + ((d >> 8) & 255)], 1u);
-        atomicAdd(&s_h[2 * kBins + ((d >> 16) & 255)], 1u);
-        atomicAdd(&s_h[3 * kBins + (d >> 24)], 1u);
-        atomicAdd(&s_h[4 * kBins + (s & 255)], 1u);
-        atomicAdd(&s_h[5 * kBins + ((s >> 8) & 255)], 1u);
-        atomicAdd(&s_h[6 * kBins + ((s >> 16) & 255)], 1u);
-        atomicAdd(&s_h[7 * kBins + (s >> 24)], 1u);
+        if (PACKETS) {
+          count32(0, lo[k]);
+          count32(4, hi[k]);
+        } else {
+          count32(0, hi[k]);
+        }
       }
     }
-    __syncthreads();
-    uint32_t *g = hist + (uint64_t)w * (kKeyDigits * kBins);
-    for (int i = threadIdx.x; i < kKeyDigits * kBins; i += BLOCK) {
-      const uint32_t c = s_h[i];
-      if (c) atomicAdd(&g[i], c);
-    }
-    __syncthreads();
   }
+  __syncthreads();
+  if (t0 < t1) flush(cur);
 }
 
 // Radix sort, step 2: exclusive scan of each 256-bin row (one wave per row).
@@ -178,6 +213,52 @@ __global__ __launch_bounds__(256) void k_hist_scan(const uint32_t *hist, uint32_
 // segment. Keys are scattered into LDS in digit order and written out from
 // there, so consecutive threads write consecutive addresses within a digit.
 // ---------------------------------------------------------------------------
+// Stable rank of each key among the wave's keys with the same digit, in
+// (item, lane) order = original order; wcnt[d] holds the wave's running count
+// of digit d (digit kBins marks a missing key). The peer mask is built on
+// 32-bit halves: for each digit bit, the ballot m is kept where this lane's bit
+// is set and its complement where it is clear. The lowest lane of each group
+// of equal digits updates the counter, so a hot digit costs one LDS update per
+// wave, not per lane.
+template <int ITEMS>
+__device__ __forceinline__ void wave_rank(const uint32_t (&dig)[ITEMS], uint32_t (&rank)[ITEMS],
+                                          uint32_t *wcnt) {
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const uint32_t d = dig[k];
+    const bool valid = d < kBins;
+    const uint64_t vm = ballot64(valid);
+    uint32_t plo = (uint32_t)vm, phi = (uint32_t)(vm >> 32);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      // all ones where this lane's bit b is set, zero where it is clear
+      const uint32_t ext = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+      const uint64_t m = ballot64(ext != 0);
+      plo &= ~((uint32_t)m ^ ext);
+      phi &= ~((uint32_t)(m >> 32) ^ ext);
+    }
+    const uint64_t peers = ((uint64_t)phi << 32) | plo;
+    if (valid) {
+      const uint32_t below = count_below(peers);
+      const uint32_t old = wcnt[d];
+      rank[k] = old + below;
+      if (below == 0) wcnt[d] = old + (uint32_t)__popcll(peers);
+    }
+  }
+}
+
+// Exclusive scan of the 256 digit totals of a tile, by one wave (4 per lane).
+__device__ __forceinline__ void local_starts(const uint32_t *tot, uint32_t *lstart, int lane) {
+  const uint32_t v0 = tot[lane * 4], v1 = tot[lane * 4 + 1], v2 = tot[lane * 4 + 2],
+                 v3 = tot[lane * 4 + 3];
+  const uint64_t mine = (uint64_t)v0 + v1 + v2 + v3;
+  const uint32_t x = (uint32_t)(wave_incl_scan(mine) - mine);
+  lstart[lane * 4] = x;
+  lstart[lane * 4 + 1] = x + v0;
+  lstart[lane * 4 + 2] = x + v0 + v1;
+  lstart[lane * 4 + 3] = x + v0 + v1 + v2;
+}
+
 // Next tile of a radix pass. With several segments of similar length, tickets
 // go layer by layer: ticket k is tile k / W of segment k % W (tickets of absent
 // tiles are skipped), so a tile's predecessor in its segment holds a ticket W
@@ -279,31 +360,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
       const uint32_t li = wbase + k * kWave + lane;
       dig[k] = li < n ? (uint32_t)(key[k] >> shift) & 255u : kBins;
     }
-    // stable rank within the wave, in (k, lane) order = original order. The
-    // peer mask is built on 32-bit halves: for each digit bit, the ballot m is
-    // kept where this lane's bit is set and its complement where it is clear.
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint32_t d = dig[k];
-      const bool valid = d < kBins;
-      const uint64_t vm = ballot64(valid);
-      uint32_t plo = (uint32_t)vm, phi = (uint32_t)(vm >> 32);
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        // all ones where this lane's bit b is set, zero where it is clear
-        const uint32_t ext = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
-        const uint64_t m = ballot64(ext != 0);
-        plo &= ~((uint32_t)m ^ ext);
-        phi &= ~((uint32_t)(m >> 32) ^ ext);
-      }
-      const uint64_t peers = ((uint64_t)phi << 32) | plo;
-      if (valid) {
-        const uint32_t below = count_below(peers);
-        const uint32_t old = s_wcnt[wv][d];
-        rank[k] = old + below;
-        if (below == 0) s_wcnt[wv][d] = old + (uint32_t)__popcll(peers);
-      }
-    }
+    wave_rank<ITEMS>(dig, rank, s_wcnt[wv]);
     __syncthreads();
     if (tid < kBins) {
       uint32_t sum = 0;
@@ -318,16 +375,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
       lb_store(a.lb + (uint64_t)t * kBins + tid, (t == first ? kLbInc : kLbAgg) | sum);
     }
     __syncthreads();
-    if (tid < kWave) {  // exclusive scan of the 256 digit totals, 4 per lane
-      const uint32_t v0 = s_tot[tid * 4], v1 = s_tot[tid * 4 + 1], v2 = s_tot[tid * 4 + 2],
-                     v3 = s_tot[tid * 4 + 3];
-      const uint64_t mine = (uint64_t)v0 + v1 + v2 + v3;
-      const uint32_t x = (uint32_t)(wave_incl_scan(mine) - mine);
-      s_lstart[tid * 4] = x;
-      s_lstart[tid * 4 + 1] = x + v0;
-      s_lstart[tid * 4 + 2] = x + v0 + v1;
-      s_lstart[tid * 4 + 3] = x + v0 + v1 + v2;
-    }
+    if (tid < kWave) local_starts(s_tot, s_lstart, tid);
     __syncthreads();
     // local counting sort of the tile into LDS; the key registers are free after
 #pragma unroll
@@ -397,6 +445,181 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Radix pass over one large segment without look-back (reduce, scan, scatter).
+//
+// With a single segment, every tile's look-back walks a long chain of tiles
+// still in flight, and each step is a round trip to memory. Here the segment
+// is cut into at most kChunks chunks of whole tiles instead: k_chunk_hist
+// counts each chunk's digits, k_chunk_scan sums them over earlier chunks per
+// digit, and k_pass_chunked sorts each chunk's tiles in order, starting from
+// those positions (plus the start of the digit's bucket) and carrying its own
+// running offsets from tile to tile. The keys are read twice, but nothing ever waits.
+// The tile count, the chunk length and the chunk count follow from the
+// segment length on the device, so a launch sized for n keys serves any
+// length up to n.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void chunk_geometry(const ChunkArgs &c, uint32_t tile, uint64_t *lo,
+                                               uint64_t *n, uint64_t *tiles, uint64_t *per) {
+  *lo = c.seg_off[0];
+  *n = c.seg_off[1] - c.seg_off[0];
+  *tiles = (*n + tile - 1) / tile;
+  const uint64_t p = (*tiles + c.chunks - 1) / c.chunks;
+  *per = p ? p : 1;
+}
+
+template <int BLOCK, bool PACKETS>
+__global__ __launch_bounds__(BLOCK) void k_chunk_hist(PassArgs a, ChunkArgs c, uint32_t tile) {
+  constexpr int C = 4;  // interleaved counter copies (see k_hist_packets)
+  __shared__ uint32_t s_h[kBins * C];
+  uint64_t lo, n, tiles, per;
+  chunk_geometry(c, tile, &lo, &n, &tiles, &per);
+  const uint32_t cp = threadIdx.x & (C - 1);
+  for (uint32_t ch = blockIdx.x; ch < c.chunks; ch += gridDim.x) {
+    for (int i = threadIdx.x; i < kBins * C; i += BLOCK) s_h[i] = 0;
+    __syncthreads();
+    const uint64_t b = min(n, (uint64_t)ch * per * tile), e = min(n, b + per * tile);
+    constexpr int R = 8;
+    for (uint64_t i0 = lo + b + threadIdx.x; i0 < lo + e; i0 += (uint64_t)R * BLOCK) {
+      uint64_t k[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const uint64_t i = i0 + (uint64_t)q * BLOCK;
+        k[q] = i < lo + e ? (PACKETS ? pack_key(a.src[i], a.dst[i]) : a.in[i]) : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        if (i0 + (uint64_t)q * BLOCK >= lo + e) break;
+        atomicAdd(&s_h[(((uint32_t)(k[q] >> a.shift)) & 255u) * C + cp], 1u);
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kBins; i += BLOCK) {
+      uint32_t v = 0;
+#pragma unroll
+      for (int q = 0; q < C; ++q) v += s_h[i * C + q];
+      c.count[(uint64_t)ch * kBins + i] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// One workgroup per digit d: prefix[ch][d] = keys with digit d in chunks
+// before ch; total[d] = keys with digit d. Each thread sums a run of
+// consecutive chunks, so one round of loads covers the whole column.
+__global__ __launch_bounds__(256) void k_chunk_scan(ChunkArgs c) {
+  __shared__ uint64_t s_tmp[4];
+  const uint32_t d = blockIdx.x;
+  const uint32_t per = (c.chunks + 255) / 256;  // <= kChunks / 256
+  constexpr int kMaxPer = kChunks / 256;
+  const uint32_t r0 = threadIdx.x * per;
+  uint32_t v[kMaxPer];
+  uint64_t sum = 0;
+#pragma unroll
+  for (int q = 0; q < kMaxPer; ++q) {
+    const uint32_t r = r0 + q;
+    v[q] = (q < (int)per && r < c.chunks) ? c.count[(uint64_t)r * kBins + d] : 0;
+    sum += v[q];
+  }
+  uint64_t tot;
+  uint64_t run = block_excl_scan<256>(sum, s_tmp, &tot);
+#pragma unroll
+  for (int q = 0; q < kMaxPer; ++q) {
+    const uint32_t r = r0 + q;
+    if (q < (int)per && r < c.chunks) c.prefix[(uint64_t)r * kBins + d] = run;
+    run += v[q];
+  }
+  if (threadIdx.x == 0) c.total[d] = tot;
+}
+
+template <int BLOCK, int ITEMS, bool PACKETS>
+__global__ __launch_bounds__(BLOCK) void k_pass_chunked(PassArgs a, ChunkArgs c) {
+  constexpr int TILE = BLOCK * ITEMS;
+  constexpr int NW = BLOCK / kWave;
+  static_assert(BLOCK >= kBins, "one thread per digit");
+  __shared__ uint64_t s_keys[TILE];
+  __shared__ uint32_t s_wcnt[NW][kBins];
+  __shared__ uint32_t s_tot[kBins];
+  __shared__ uint32_t s_lstart[kBins];
+  __shared__ uint64_t s_gbase[kBins];
+  __shared__ uint32_t s_chunk;
+
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const uint32_t shift = a.shift;
+  const uint32_t wbase = wv * (kWave * ITEMS);
+  __shared__ uint64_t s_dbase[kBins];
+  __shared__ uint64_t s_tmp[NW];
+  uint64_t lo, nk, tiles, per;
+  chunk_geometry(c, TILE, &lo, &nk, &tiles, &per);
+  {  // start of each digit's bucket: segment start + keys with a smaller digit
+    uint64_t tot;
+    const uint64_t x = block_excl_scan<BLOCK>(tid < kBins ? c.total[tid] : 0, s_tmp, &tot);
+    if (tid < kBins) s_dbase[tid] = lo + x;
+  }
+
+  for (;;) {
+    if (tid == 0) s_chunk = atomicAdd(a.ticket, 1u);
+    for (int i = tid; i < NW * kBins; i += BLOCK) (&s_wcnt[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t ch = s_chunk;
+    if (ch >= c.chunks) break;
+    const uint64_t t0 = min(tiles, (uint64_t)ch * per), t1 = min(tiles, t0 + per);
+    if (tid < kBins) s_gbase[tid] = s_dbase[tid] + c.prefix[(uint64_t)ch * kBins + tid];
+    uint64_t key[ITEMS];
+    uint32_t n = 0;
+    if (t0 < t1) {
+      const uint64_t start = lo + t0 * TILE;
+      n = (uint32_t)min((uint64_t)TILE, lo + nk - start);
+      pass_load<ITEMS, PACKETS>(a, start, n, wbase, lane, TILE, key);
+    }
+    for (uint64_t t = t0; t < t1; ++t) {
+      uint32_t dig[ITEMS];
+      uint32_t rank[ITEMS];
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t li = wbase + k * kWave + lane;
+        dig[k] = li < n ? (uint32_t)(key[k] >> shift) & 255u : kBins;
+      }
+      wave_rank<ITEMS>(dig, rank, s_wcnt[wv]);
+      __syncthreads();
+      if (tid < kBins) {
+        uint32_t sum = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+          const uint32_t v = s_wcnt[q][tid];
+          s_wcnt[q][tid] = sum;
+          sum += v;
+        }
+        s_tot[tid] = sum;
+      }
+      __syncthreads();
+      if (tid < kWave) local_starts(s_tot, s_lstart, tid);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t d = dig[k];
+        if (d < kBins) s_keys[s_lstart[d] + s_wcnt[wv][d] + rank[k]] = key[k];
+      }
+      __syncthreads();
+      for (int i = tid; i < NW * kBins; i += BLOCK) (&s_wcnt[0][0])[i] = 0;
+      const uint32_t n_cur = n;
+      if (t + 1 < t1) {  // the next tile's keys load while this one is written
+        const uint64_t start = lo + (t + 1) * TILE;
+        n = (uint32_t)min((uint64_t)TILE, lo + nk - start);
+        pass_load<ITEMS, PACKETS>(a, start, n, wbase, lane, TILE, key);
+      }
+      for (uint32_t i = tid; i < n_cur; i += BLOCK) {
+        const uint64_t x = s_keys[i];
+        const uint32_t d = (uint32_t)(x >> shift) & 255u;
+        a.out[s_gbase[d] + (i - s_lstart[d])] = x;
+      }
+      __syncthreads();
+      if (tid < kBins) s_gbase[tid] += s_tot[tid];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // First index in (lo, hi] whose key differs from K, given keys[lo] == K in a
 // sorted array (hi if none). The whole calling wave searches together: 64
 // probes per round trip (the next 64 positions, then 64 exponentially spaced
@@ -453,7 +676,6 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
   __shared__ uint16_t s_hpos[TILE];   // link head positions in the tile
   __shared__ uint16_t s_rpos[TILE];   // row head positions
   __shared__ uint16_t s_rlr[TILE];    // tile-local link rank of each row head
-  __shared__ uint32_t s_ch[kColDigits * kBins];
   __shared__ uint64_t s_tmp[BLOCK / kWave];
   __shared__ uint64_t s_L0, s_R0, s_trail, s_base;
   __shared__ uint32_t s_tile;
@@ -462,8 +684,6 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
   const uint64_t total = a.tile_off[a.W];
   for (;;) {
     if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
-    if (a.col_hist)
-      for (int i = tid; i < kColDigits * kBins; i += BLOCK) s_ch[i] = 0;
     __syncthreads();
     const uint32_t t = s_tile;
     if (t >= total) break;
@@ -588,26 +808,11 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
         a.win_counts[wpos + r] = cnt;
       }
       if (a.items) a.items[L] = (K << 32) | cnt;
-      if (a.col_hist) {
-        const uint32_t d = (uint32_t)K;
-        atomicAdd(&s_ch[0 * kBins + (d & 255)], 1u);
-        atomicAdd(&s_ch[1 * kBins + ((d >> 8) & 255)], 1u);
-        atomicAdd(&s_ch[2 * kBins + ((d >> 16) & 255)], 1u);
-        atomicAdd(&s_ch[3 * kBins + (d >> 24)], 1u);
-      }
     }
     if (a.rpos) {
       for (uint32_t q = tid; q < TR; q += BLOCK) {
         a.rpos[R0 + q] = start + s_rpos[q];
         a.rlink[R0 + q] = L0 + s_rlr[q];
-      }
-    }
-    __syncthreads();
-    if (a.col_hist) {
-      uint32_t *g = a.col_hist + (uint64_t)w * (kColDigits * kBins);
-      for (int i = tid; i < kColDigits * kBins; i += BLOCK) {
-        const uint32_t c = s_ch[i];
-        if (c) atomicAdd(&g[i], c);
       }
     }
     __syncthreads();
@@ -617,7 +822,7 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
 // ---------------------------------------------------------------------------
 // Run reduction over a sorted array with explicit values.
 // mode 0 (rows of a matrix): group = source, value = A(i,j); every link also
-//   emits its column item dst<<32|count and the item's digit histograms.
+//   emits its column item dst<<32|count.
 // mode 1 (columns): group = destination of a sorted column item, value = the
 //   item's count.
 // Heads are compacted with a two-channel look-back (heads, value prefix); each
@@ -633,7 +838,6 @@ __global__ __launch_bounds__(256) void k_runs(RunArgs a) {
   __shared__ uint32_t s_v[TILE];       // value (< 2^32)
   __shared__ uint16_t s_hp[TILE];      // head local positions
   __shared__ uint32_t s_hv[TILE];      // tile-local exclusive value prefix at head
-  __shared__ uint32_t s_ch[kColDigits * kBins];
   __shared__ uint64_t s_tmp[BLOCK / kWave];
   __shared__ uint64_t s_H0, s_V0;
   __shared__ uint32_t s_tile;
@@ -642,8 +846,6 @@ __global__ __launch_bounds__(256) void k_runs(RunArgs a) {
   const uint64_t total = a.tile_off[a.W];
   for (;;) {
     if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
-    if (MODE == 0 && a.col_hist)
-      for (int i = tid; i < kColDigits * kBins; i += BLOCK) s_ch[i] = 0;
     __syncthreads();
     const uint32_t t = s_tile;
     if (t >= total) break;
@@ -660,13 +862,6 @@ __global__ __launch_bounds__(256) void k_runs(RunArgs a) {
         const uint64_t c = a.counts[start + i];
         s_v[i] = (uint32_t)c;
         if (a.items) a.items[start + i] = (k << 32) | c;
-        if (a.col_hist) {
-          const uint32_t d = (uint32_t)k;
-          atomicAdd(&s_ch[0 * kBins + (d & 255)], 1u);
-          atomicAdd(&s_ch[1 * kBins + ((d >> 8) & 255)], 1u);
-          atomicAdd(&s_ch[2 * kBins + ((d >> 16) & 255)], 1u);
-          atomicAdd(&s_ch[3 * kBins + (d >> 24)], 1u);
-        }
       } else {
         s_v[i] = (uint32_t)k;
       }
@@ -731,14 +926,6 @@ __global__ __launch_bounds__(256) void k_runs(RunArgs a) {
     for (uint32_t h = tid; h < TH; h += BLOCK) {
       a.hpos[H0 + h] = start + s_hp[h];
       a.hval[H0 + h] = V0 + s_hv[h];
-    }
-    __syncthreads();
-    if (MODE == 0 && a.col_hist) {
-      uint32_t *g = a.col_hist + (uint64_t)w * (kColDigits * kBins);
-      for (int i = tid; i < kColDigits * kBins; i += BLOCK) {
-        const uint32_t c = s_ch[i];
-        if (c) atomicAdd(&g[i], c);
-      }
     }
     __syncthreads();
   }
@@ -1071,9 +1258,20 @@ hipError_t launch_hist_packets(const uint32_t *src, const uint32_t *dst, const u
                                uint32_t *hist, hipStream_t s) {
   static uint64_t cap[64];
   const int d = device_id();
-  if (!cap[d]) cap[d] = resident(k_hist_packets<256>, 256);
-  NS_LAUNCH(k_hist_packets<256>, dim3(clamp_grid(max_tiles, cap[d])), dim3(256), s,
-                     src, dst, seg_off, tile_off, W, hist);
+  if (!cap[d]) cap[d] = resident(k_hist<256, true>, 256);
+  NS_LAUNCH((k_hist<256, true>), dim3(clamp_grid(max_tiles, cap[d])), dim3(256), s, src, dst,
+            nullptr, seg_off, tile_off, W, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_hist_items(const uint64_t *items, const uint64_t *seg_off,
+                             const uint64_t *tile_off, uint32_t W, uint64_t max_tiles,
+                             uint32_t *hist, hipStream_t s) {
+  static uint64_t cap[64];
+  const int d = device_id();
+  if (!cap[d]) cap[d] = resident(k_hist<256, false>, 256);
+  NS_LAUNCH((k_hist<256, false>), dim3(clamp_grid(max_tiles, cap[d])), dim3(256), s, nullptr,
+            nullptr, items, seg_off, tile_off, W, hist);
   return hipGetLastError();
 }
 
@@ -1102,6 +1300,40 @@ hipError_t launch_pass(const SortShape &sh, const PassArgs &a, uint64_t max_tile
   return hipErrorInvalidValue;
 }
 
+template <int B, int I, bool P>
+static hipError_t pass_chunked_impl(const PassArgs &a, ChunkArgs c, uint64_t max_keys,
+                                    int count_kind, hipStream_t s) {
+  static uint64_t cap[64];
+  const int d = device_id();
+  if (!cap[d]) cap[d] = resident(k_pass_chunked<B, I, P>, B);
+  // one chunk per resident workgroup (at most NS_CHUNKS_PER_CU per CU), each
+  // of at least two tiles: every chunk starts at once and none waits for a
+  // free slot
+  uint64_t ch = (uint64_t)NS_CHUNKS_PER_CU * cu_count();
+  if (ch > cap[d]) ch = cap[d];
+  if (ch > kChunks) ch = kChunks;
+  const uint64_t tiles = (max_keys + B * I - 1) / (B * I);
+  if (ch > tiles / 2) ch = tiles / 2;
+  c.chunks = (uint32_t)(ch ? ch : 1);
+  const int kind = tl_timing_kind;
+  if (kind >= 0) tl_timing_kind = count_kind;
+  NS_LAUNCH((k_chunk_hist<256, P>), dim3(c.chunks), dim3(256), s, a, c, (uint32_t)(B * I));
+  NS_LAUNCH(k_chunk_scan, dim3(kBins), dim3(256), s, c);
+  tl_timing_kind = kind;
+  NS_LAUNCH((k_pass_chunked<B, I, P>), dim3(c.chunks), dim3(B), s, a, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_chunked(const SortShape &sh, const PassArgs &a, const ChunkArgs &c,
+                               uint64_t max_keys, int count_kind, hipStream_t s) {
+  const bool P = a.src != nullptr;
+  if (sh.block == 256 && sh.items == 8) return P ? pass_chunked_impl<256, 8, true>(a, c, max_keys, count_kind, s) : pass_chunked_impl<256, 8, false>(a, c, max_keys, count_kind, s);
+  if (sh.block == 256 && sh.items == 16) return P ? pass_chunked_impl<256, 16, true>(a, c, max_keys, count_kind, s) : pass_chunked_impl<256, 16, false>(a, c, max_keys, count_kind, s);
+  if (sh.block == 512 && sh.items == 8) return P ? pass_chunked_impl<512, 8, true>(a, c, max_keys, count_kind, s) : pass_chunked_impl<512, 8, false>(a, c, max_keys, count_kind, s);
+  if (sh.block == 512 && sh.items == 16) return P ? pass_chunked_impl<512, 16, true>(a, c, max_keys, count_kind, s) : pass_chunked_impl<512, 16, false>(a, c, max_keys, count_kind, s);
+  return hipErrorInvalidValue;
+}
+
 template <int I>
 static hipError_t rle_impl(const RleArgs &a, uint64_t max_tiles, hipStream_t s) {
   static uint64_t cap[64];
@@ -1114,6 +1346,7 @@ static hipError_t rle_impl(const RleArgs &a, uint64_t max_tiles, hipStream_t s) 
 hipError_t launch_rle(const ScanShape &sh, const RleArgs &a, uint64_t max_tiles, hipStream_t s) {
   if (sh.items == 4) return rle_impl<4>(a, max_tiles, s);
   if (sh.items == 8) return rle_impl<8>(a, max_tiles, s);
+  if (sh.items == 16) return rle_impl<16>(a, max_tiles, s);
   return hipErrorInvalidValue;
 }
 
@@ -1130,6 +1363,7 @@ hipError_t launch_runs(const ScanShape &sh, int mode, const RunArgs &a, uint64_t
                        hipStream_t s) {
   if (sh.items == 4) return mode == 0 ? runs_impl<4, 0>(a, max_tiles, s) : runs_impl<4, 1>(a, max_tiles, s);
   if (sh.items == 8) return mode == 0 ? runs_impl<8, 0>(a, max_tiles, s) : runs_impl<8, 1>(a, max_tiles, s);
+  if (sh.items == 16) return mode == 0 ? runs_impl<16, 0>(a, max_tiles, s) : runs_impl<16, 1>(a, max_tiles, s);
   return hipErrorInvalidValue;
 }
 

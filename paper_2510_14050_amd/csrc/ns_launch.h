@@ -40,6 +40,10 @@ hipError_t launch_tiles(const uint64_t *seg_off, uint32_t W, uint32_t ta, uint64
 hipError_t launch_hist_packets(const uint32_t *src, const uint32_t *dst, const uint64_t *seg_off,
                                const uint64_t *tile_off, uint32_t W, uint64_t max_tiles,
                                uint32_t *hist, hipStream_t s);
+// digit histograms (4 digits of dst) of column items dst<<32|count, per segment
+hipError_t launch_hist_items(const uint64_t *items, const uint64_t *seg_off,
+                             const uint64_t *tile_off, uint32_t W, uint64_t max_tiles,
+                             uint32_t *hist, hipStream_t s);
 // exclusive scan of rows of 256 bins
 hipError_t launch_hist_scan(const uint32_t *hist, uint32_t *base, uint64_t rows, hipStream_t s);
 
@@ -60,6 +64,21 @@ struct PassArgs {
 };
 hipError_t launch_pass(const SortShape &sh, const PassArgs &a, uint64_t max_tiles, hipStream_t s);
 
+// --- radix pass over one large segment: reduce, scan, scatter (no look-back) ---
+constexpr uint32_t kChunks = 1024;  // most chunks per pass (rows of count / prefix)
+struct ChunkArgs {
+  const uint64_t *seg_off;  // [2]: the segment is [seg_off[0], seg_off[1])
+  uint32_t chunks;          // set by the launcher (<= kChunks)
+  uint32_t *count;          // [kChunks][256] digit counts per chunk
+  uint64_t *prefix;         // [kChunks][256] keys of the digit in earlier chunks
+  uint64_t *total;          // [256] keys per digit
+};
+// Sorts at most max_keys keys. a.seg_off / tile_off / W / base / lb are unused;
+// a.ticket must start at zero. When kernel timing is on, the counting and
+// scan kernels are recorded under count_kind.
+hipError_t launch_pass_chunked(const SortShape &sh, const PassArgs &a, const ChunkArgs &c,
+                               uint64_t max_keys, int count_kind, hipStream_t s);
+
 // --- run-length encoding of sorted packet keys ------------------------------------
 struct RleArgs {
   const uint64_t *keys;
@@ -75,7 +94,6 @@ struct RleArgs {
   uint64_t *seg_base;  // [W] flagged words: global link index at each segment start
   uint64_t *rpos;      // nullable: packet position of each row head (+ sentinel)
   uint64_t *rlink;     // link index of each row head (+ sentinel)
-  uint32_t *col_hist;  // nullable [W][4][256]
   uint64_t *link_off;  // [W+1]
   uint64_t *row_off;   // [W+1]
   uint64_t *nnz_out;   // nullable: total links
@@ -98,7 +116,6 @@ struct RunArgs {
   uint64_t *hval;            // exclusive value prefix at head (+ sentinel)
   uint64_t *head_off;        // [W+1]
   uint64_t *items;           // mode 0, nullable
-  uint32_t *col_hist;        // mode 0, nullable
   uint64_t *lb;              // [tiles][2]
   uint32_t *ticket;
 };

@@ -48,7 +48,8 @@ class MatrixView(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("sort_block", ctypes.c_uint32), ("sort_items", ctypes.c_uint32),
-                ("digit_bits", ctypes.c_uint32), ("scan_items", ctypes.c_uint32)]
+                ("digit_bits", ctypes.c_uint32), ("scan_items", ctypes.c_uint32),
+                ("chunked_min", ctypes.c_uint64)]
 
 
 class RollingView(ctypes.Structure):
@@ -69,7 +70,13 @@ EXPORTS = ("ns_workspace_size", "ns_build_matrix", "ns_accumulate", "ns_stats",
 
 # kernel kinds of ns_timing_read
 KINDS = ("fill", "tiles", "hist", "hist_scan", "pass0", "pass", "col_pass", "rle", "runs",
-         "segmax", "finalize", "merge")
+         "segmax", "finalize", "merge", "chunk_count", "pass0_chunked", "pass_chunked",
+         "col_pass_chunked")
+# default single-segment size from which sorts use the chunked passes
+# (ns_tuning_t.chunked_min = 0)
+CHUNKED_MIN_DEFAULT = 1 << 24
+# launch shape (workgroup size, keys per thread) of the chunked passes
+CHUNKED_SHAPE = (512, 16)
 
 _lib = None
 
@@ -258,8 +265,8 @@ class BatchMatrices:
                            self.counts[start:start + max(n, 1)], self.nnz[w:w + 1], n, n)
 
 
-def tuning(sort_block=0, sort_items=0, digit_bits=0, scan_items=0) -> Tuning:
-    return Tuning(sort_block, sort_items, digit_bits, scan_items)
+def tuning(sort_block=0, sort_items=0, digit_bits=0, scan_items=0, chunked_min=0) -> Tuning:
+    return Tuning(sort_block, sort_items, digit_bits, scan_items, chunked_min)
 
 
 def batch_stats(src, dst, offsets, out, ws: Workspace, agg: Matrix | None = None,

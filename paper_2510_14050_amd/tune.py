@@ -19,7 +19,7 @@ from . import ns
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.environ.get("NS_TUNE_CACHE", os.path.join(HERE, "tune_cache.json"))
 
-SHAPES = [(256, 8, 4), (256, 8, 8), (256, 16, 4), (256, 16, 8), (512, 8, 8), (512, 16, 8)]
+SHAPES = [(256, 8, 8), (256, 16, 8), (512, 8, 8), (512, 16, 8), (512, 16, 16)]
 
 
 def size_class(packets: int, windows: int) -> str:
@@ -92,7 +92,7 @@ def main():
 
     from . import synth
     p = argparse.ArgumentParser()
-    p.add_argument("--workloads", default="windows64,uneven1024,one_window")
+    p.add_argument("--workloads", default="windows64,uneven1024,one_window,aggregate_2p30")
     p.add_argument("--reps", type=int, default=10)
     args = p.parse_args()
     dev = torch.device("cuda:0")

@@ -172,6 +172,50 @@ def test_batch_tuning_shapes(gpu, shape):
     check_batch(ns, src, dst, *res)
 
 
+CHUNKED_CASES = {
+    "ragged_agg": RAGGED,
+    "one_window": [300_001],
+    "one_empty": [0],
+    "one_packet": [1],
+    "one_tile_plus": [4097],
+}
+
+
+@pytest.mark.parametrize("shape", [(256, 8), (256, 16), (512, 8), (512, 16)])
+@pytest.mark.parametrize("case", list(CHUNKED_CASES))
+def test_batch_chunked_single_segment(gpu, case, shape):
+    """Single segments (the aggregate, or a batch of one window) forced onto
+    the chunked passes: same results as the oracle."""
+    torch, ns = gpu
+    sizes = CHUNKED_CASES[case]
+    say("chunked single segment", case, shape)
+    src, dst = zipf_packets(31 + len(sizes), sum(sizes), pool=2500)
+    t = ns.tuning(sort_block=shape[0], sort_items=shape[1], chunked_min=1)
+    for graph in (True, False):
+        res = run_batch(torch, ns, src, dst, sizes, tune=t, graph=graph)
+        check_batch(ns, src, dst, *res)
+
+
+@pytest.mark.parametrize("name", ["hot_link", "extremes", "scanner", "identical"])
+def test_batch_chunked_patterns(gpu, name):
+    torch, ns = gpu
+    src, dst = {p[0]: p[1:] for p in patterns()}[name]
+    say("chunked pattern", name)
+    t = ns.tuning(chunked_min=1)
+    res = run_batch(torch, ns, src, dst, [src.size], tune=t)
+    check_batch(ns, src, dst, *res)
+
+
+def test_single_window_above_chunked_threshold(gpu):
+    """A window of 2^24 + 12345 packets takes the chunked passes by default
+    (build_matrix and the statistics of its matrix)."""
+    torch, ns = gpu
+    n = (1 << 24) + 12345
+    say("single window, chunked by default, n=", n)
+    src, dst = zipf_packets(2024, n, pool=1 << 18, s=1.1)
+    build_and_check(torch, ns, src, dst)
+
+
 def test_graph_replays_match_eager(gpu):
     """A cached graph replayed on new data in the same buffers, with eager
     work and synchronisation between replays, matches the oracle each time."""
