@@ -16,6 +16,7 @@ GPU.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -97,7 +98,8 @@ def main():
     sort_block = shape.sort_block if shape else 256
     sort_items = shape.sort_items if shape else 16
     log(f"launch shape: radix {sort_block}x{sort_items}, scan 256x"
-        f"{shape.scan_items if shape else 8} ({'autotuned' if shape else 'default'})")
+        f"{shape.scan_items if shape else 8} "
+        f"({'autotuned' if shape else 'default: no tuning cache entry'} for {tune._device_name()})")
 
     def step():
         ns.batch_stats(src_t, dst_t, off_t, out, ws, agg=agg, agg_stats=agg_stats, tune=shape)
@@ -127,7 +129,7 @@ def main():
     ns.timing_enable(False)
     ns.timing_reset()
     links_windows = int(got[:, 1].sum())
-    roof = radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block, sort_items)
+    roof = radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block, sort_items, args.workload)
     breakdown = {k: {"ms": round(v[0], 4), "launches": v[1]} for k, v in kt.items()}
     log("kernel breakdown (eager, ms):", json.dumps(breakdown))
 
@@ -229,7 +231,39 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block, sort_items):
+def kernel_source_sha256() -> str:
+    """Hash of the HIP sources, to tell whether stored counter data still
+    describes the kernels that run."""
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2510_14050_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 memory-counter summary (FETCH_SIZE and WRITE_SIZE passes, each
+    scaled by what it reads for a 1 GiB copy), or None when the summary is
+    missing or was taken on other kernel sources."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_sha256():
+        return None
+    for e in t.get("entries", []):
+        if e["workload"] == workload and e["kernel"] == kernel:
+            return e["traffic_bytes_per_launch"]
+    return None
+
+
+def radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block, sort_items, workload):
     """Roofline of the dominant kernel, the radix pass (key passes 2-8 and the
     four column passes; the first key pass reads packets and is timed apart).
     Two kernels implement it: k_pass (decoupled look-back, every multi-segment
@@ -258,12 +292,13 @@ def radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block, sort_items):
         rows[name] = {"kernel": f["kernel"], "achieved": round(ach, 1),
                       "frac": round(ach / PEAK_HBM_GBS, 4), "total_ms": round(ms, 4),
                       "launches": n, "avg_launch_ms": round(ms / n, 5),
-                      "algorithmic_bytes_per_launch": round(byts / n)}
+                      "algorithmic_bytes_per_launch": round(byts / n),
+                      "traffic": profiled_traffic(workload, f["kernel"])}
     if not rows:
         return None
     top = max(rows.values(), key=lambda r: r["total_ms"])
     return {"bound": "hbm", "achieved": top["achieved"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": top["frac"], "traffic": None, "kernel": top["kernel"],
+            "frac": top["frac"], "traffic": top["traffic"], "kernel": top["kernel"],
             "avg_launch_ms": top["avg_launch_ms"], "launches": top["launches"],
             "algorithmic_bytes_per_launch": top["algorithmic_bytes_per_launch"],
             "kernels": rows}

@@ -27,8 +27,11 @@ def size_class(packets: int, windows: int) -> str:
 
 
 def _device_name() -> str:
+    """Cache key of the current device: ISA and compute-unit count (the
+    marketing name is not stable across tools that wrap the runtime)."""
     import torch
-    return torch.cuda.get_device_name(0)
+    p = torch.cuda.get_device_properties(0)
+    return f"{p.gcnArchName.split(':')[0]}/{p.multi_processor_count}CU"
 
 
 def _load_cache() -> dict:
