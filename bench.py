@@ -221,6 +221,7 @@ def main():
                    "outputs": "per-window 8 stats + aggregate matrix + aggregate 8 stats",
                    "submission": "one HIP graph (ns_batch_stats)"},
         "roofline": roof,
+        "path": path_rates(args.workload, N, W, got, got_agg, ms_step),
         "cpu_baseline": cpu,
         "plain": plain,
         "batched_vs_plain": round(value / plain["value"], 2) if plain else None,
@@ -261,6 +262,58 @@ def profiled_traffic(workload: str, kernel: str):
         if e["workload"] == workload and e["kernel"] == kernel:
             return e["traffic_bytes_per_launch"]
     return None
+
+
+def model_bytes(N, W, got, got_agg):
+    """Bytes the design as built moves for one step (per-window pipeline plus
+    the aggregate pipeline), from the measured links, sources and destinations:
+      multi-segment sort (look-back): 8 (histogram) + 8 x 16 (key passes)
+      single segment >= CHUNKED_MIN_DEFAULT (chunked): 8 x (8 + 16)
+      run-length: 8 read + 24 per link (items + the per-window matrix, or the
+        aggregate's keys and counts) + 16 per row head
+      row maxima: 16 per row head
+      columns: 8 per link (histogram; look-back only) + 4 x 16 per link
+        (passes; +8 each when chunked) + 8 per link (run reduce) + 16 per
+        column head, and 16 per column head for the maxima."""
+    from paper_2510_14050_amd import ns
+    cmin = ns.CHUNKED_MIN_DEFAULT
+    def pipe(n, links, rows, cols, chunked):
+        b = (8 * 24 if chunked else 8 + 8 * 16) * n
+        b += 8 * n + 24 * links + 16 * rows + 16 * rows
+        b += (4 * 24 if chunked else 8 + 4 * 16) * links + 8 * links + 32 * cols
+        return b
+    win = pipe(N, int(got[:, 1].sum()), int(got[:, 2].sum()), int(got[:, 3].sum()),
+               W == 1 and N >= cmin)
+    agg = pipe(N, int(got_agg[1]), int(got_agg[2]), int(got_agg[3]), N >= cmin)
+    return win + agg
+
+
+def path_rates(workload, N, W, got, got_agg, ms_step):
+    """Whole-step rates: measured memory traffic (rocprofv3 FETCH_SIZE +
+    WRITE_SIZE of every library kernel of one step, scaled by a 1 GiB copy;
+    null unless taken on these sources), the model bytes of the design, and
+    the floor of reading every packet once, each divided by the step time."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
+    measured = None
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        if t.get("source_sha256") == kernel_source_sha256():
+            measured = t.get("step_traffic_bytes", {}).get(workload)
+    except (OSError, ValueError):
+        pass
+    sec = ms_step * 1e-3
+    M = model_bytes(N, W, got, got_agg)
+    F = 8 * N + 64 * W
+    out = {"step_ms": round(ms_step, 4), "peak_gbs": PEAK_HBM_GBS,
+           "model_bytes": M, "model_bytes_per_packet": round(M / max(N, 1), 2),
+           "model_gbs": round(M / sec / 1e9, 1), "model_frac": round(M / sec / 1e9 / PEAK_HBM_GBS, 4),
+           "floor_bytes": F, "floor_gbs": round(F / sec / 1e9, 1),
+           "measured_bytes": measured, "measured_gbs": None, "measured_frac": None}
+    if measured:
+        out["measured_gbs"] = round(measured / sec / 1e9, 1)
+        out["measured_frac"] = round(measured / sec / 1e9 / PEAK_HBM_GBS, 4)
+    return out
 
 
 def radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block, sort_items, workload):

@@ -186,9 +186,21 @@ int enqueue_columns(Ws &ws, const Shapes &sh, uint64_t *items, uint64_t *tmp,
   const bool chunked = W == 1 && max_items >= sh.chunked_min;
   uint64_t *t_chist = ws.at<uint64_t>(L.t_hist);  // free again once the key histograms are done
   HIP_TRY(timed(K_TILES, s, [&] { return launch_tiles(link_off, W, sh.sort.tile(), t_csort, sh.scan.tile(), t_run, kHistTile, t_chist, s); }));
+  uint64_t *lbs = ws.at<uint64_t>(L.lbs);
+  uint64_t *hpos = ws.at<uint64_t>(L.HA), *hval = ws.at<uint64_t>(L.HB);
+  uint64_t *col_off = ws.at<uint64_t>(L.col_off);
+  const uint64_t run_tiles = max_items / sh.scan.tile() + W + 1;
+  {
+    FillList f;
+    if (!chunked) f.add32(chist, (uint64_t)W * kColDigits * kBins);
+    f.add64(lbs, run_tiles * 2);
+    f.add64(col_off, (uint64_t)W + 1);
+    f.add64(hpos, 1);
+    f.add64(hval, 1);
+    HIP_TRY(launch_fill_multi(f, s));
+  }
   if (!chunked) {
     const uint64_t hist_tiles = max_items / kHistTile + W + 1;
-    HIP_TRY(launch_fill32(chist, (uint64_t)W * kColDigits * kBins, 0, s));
     HIP_TRY(timed(K_HIST, s, [&] { return launch_hist_items(items, link_off, t_chist, W, hist_tiles, chist, s); }));
     HIP_TRY(timed(K_HSCAN, s, [&] { return launch_hist_scan(chist, cbase, (uint64_t)W * kColDigits, s); }));
   }
@@ -222,14 +234,6 @@ int enqueue_columns(Ws &ws, const Shapes &sh, uint64_t *items, uint64_t *tmp,
     return hipSuccess;
   }, kColDigits));
   // 4 passes: sorted items are back in `items`
-  uint64_t *lbs = ws.at<uint64_t>(L.lbs);
-  uint64_t *hpos = ws.at<uint64_t>(L.HA), *hval = ws.at<uint64_t>(L.HB);
-  uint64_t *col_off = ws.at<uint64_t>(L.col_off);
-  const uint64_t run_tiles = max_items / sh.scan.tile() + W + 1;
-  HIP_TRY(launch_fill64(lbs, run_tiles * 2, 0, s));
-  HIP_TRY(launch_fill64(col_off, (uint64_t)W + 1, 0, s));
-  HIP_TRY(launch_fill64(hpos, 1, 0, s));
-  HIP_TRY(launch_fill64(hval, 1, 0, s));
   RunArgs r{};
   r.keys = items;
   r.seg_off = link_off;
@@ -278,17 +282,19 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
   // histograms nor the look-back words (the column passes follow suit)
   const bool chunked = W == 1 && N >= sh.chunked_min;
 
-  if (!chunked) HIP_TRY(launch_fill32(hist, (uint64_t)W * kKeyDigits * kBins, 0, s));
-  if (want_stats) {
-    HIP_TRY(launch_fill64(o.stats, (uint64_t)W * 8, 0, s));
-  }
-  if (!chunked) HIP_TRY(launch_fill64(lb[0], sort_tiles * kBins, 0, s));
-  HIP_TRY(launch_fill64(link_off, (uint64_t)W + 1, 0, s));
-  HIP_TRY(launch_fill64(row_off, (uint64_t)W + 1, 0, s));
-  if (o.nnz) HIP_TRY(launch_fill64(o.nnz, 1, 0, s));
-  if (o.win_keys) {
-    HIP_TRY(launch_fill64(o.win_nnz, W, 0, s));
-    HIP_TRY(launch_fill64(ws.at<uint64_t>(L.seg_base), W, 0, s));
+  {
+    FillList f;
+    if (!chunked) f.add32(hist, (uint64_t)W * kKeyDigits * kBins);
+    if (want_stats) f.add64(o.stats, (uint64_t)W * 8);
+    if (!chunked) f.add64(lb[0], sort_tiles * kBins);
+    f.add64(link_off, (uint64_t)W + 1);
+    f.add64(row_off, (uint64_t)W + 1);
+    if (o.nnz) f.add64(o.nnz, 1);
+    if (o.win_keys) {
+      f.add64(o.win_nnz, W);
+      f.add64(ws.at<uint64_t>(L.seg_base), W);
+    }
+    HIP_TRY(launch_fill_multi(f, s));
   }
   HIP_TRY(launch_tiles(seg_off, W, sh.sort.tile(), t_sort, kHistTile, t_hist, sh.scan.tile(),
                        t_rle, s));
@@ -334,14 +340,18 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
   uint64_t *sorted = buf[(kKeyDigits - 1) & 1];  // == sort_b
   // run-length encoding (+ rows and column items when statistics are wanted)
   uint64_t *lbs = ws.at<uint64_t>(L.lbs);
-  HIP_TRY(launch_fill64(lbs, rle_tiles * 2, 0, s));
   uint64_t *items = nullptr, *rpos = nullptr, *rlink = nullptr;
-  if (want_stats) {
-    items = ws.at<uint64_t>(L.KA) == sorted ? ws.at<uint64_t>(L.KB) : ws.at<uint64_t>(L.KA);
-    rpos = ws.at<uint64_t>(L.HA);
-    rlink = ws.at<uint64_t>(L.HB);
-    HIP_TRY(launch_fill64(rpos, 1, 0, s));
-    HIP_TRY(launch_fill64(rlink, 1, 0, s));
+  {
+    FillList f;
+    f.add64(lbs, rle_tiles * 2);
+    if (want_stats) {
+      items = ws.at<uint64_t>(L.KA) == sorted ? ws.at<uint64_t>(L.KB) : ws.at<uint64_t>(L.KA);
+      rpos = ws.at<uint64_t>(L.HA);
+      rlink = ws.at<uint64_t>(L.HB);
+      f.add64(rpos, 1);
+      f.add64(rlink, 1);
+    }
+    HIP_TRY(launch_fill_multi(f, s));
   }
   RleArgs r{};
   r.keys = sorted;
@@ -388,12 +398,16 @@ int enqueue_matrix_stats(Ws &ws, const Shapes &sh, const ns_matrix_t *m, uint64_
   uint64_t *lbs = ws.at<uint64_t>(L.lbs);
   const uint64_t run_tiles = cap / sh.scan.tile() + 2;
 
-  HIP_TRY(launch_fill64(stats, 8, 0, s));
-  HIP_TRY(launch_fill64(ws.at<uint64_t>(L.lb0), (cap / sh.sort.tile() + 2) * kBins, 0, s));
-  HIP_TRY(launch_fill64(lbs, run_tiles * 2, 0, s));
-  HIP_TRY(launch_fill64(row_off, 2, 0, s));
-  HIP_TRY(launch_fill64(hpos, 1, 0, s));
-  HIP_TRY(launch_fill64(hval, 1, 0, s));
+  {
+    FillList f;
+    f.add64(stats, 8);
+    f.add64(ws.at<uint64_t>(L.lb0), (cap / sh.sort.tile() + 2) * kBins);
+    f.add64(lbs, run_tiles * 2);
+    f.add64(row_off, 2);
+    f.add64(hpos, 1);
+    f.add64(hval, 1);
+    HIP_TRY(launch_fill_multi(f, s));
+  }
   HIP_TRY(launch_seg1(seg, m->nnz, cap, s));
   HIP_TRY(launch_seg1(link_off, m->nnz, cap, s));
   HIP_TRY(timed(K_TILES, s, [&] { return launch_tiles(seg, 1, sh.scan.tile(), t_run, 1, nullptr, 1, nullptr, s); }));

@@ -41,6 +41,18 @@ __global__ void k_fill32(uint32_t *p, uint64_t n, uint32_t v) {
     p[i] = v;
 }
 
+// Several fills in one launch (each region written with its own value).
+__global__ void k_fill_multi(FillList f) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint32_t q = 0; q < f.count; ++q) {
+    const FillEntry e = f.e[q];
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < e.n; i += stride) {
+      if (e.wide) static_cast<uint64_t *>(e.p)[i] = e.v;
+      else static_cast<uint32_t *>(e.p)[i] = (uint32_t)e.v;
+    }
+  }
+}
+
 // seg = {0, n}, with n read from the device when n_dev is given and clamped to
 // the host-known bound `n` (a device count never drives accesses past it)
 __global__ void k_seg1(uint64_t *seg, const uint64_t *n_dev, uint64_t n) {
@@ -1232,6 +1244,14 @@ hipError_t launch_fill64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const uint32_t g = clamp_grid((n + 255) / 256, 4096);
   NS_LAUNCH(k_fill64, dim3(g), dim3(256), s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_multi(const FillList &f, hipStream_t s) {
+  uint64_t most = 0;
+  for (uint32_t q = 0; q < f.count; ++q) most = f.e[q].n > most ? f.e[q].n : most;
+  if (most == 0) return hipSuccess;
+  NS_LAUNCH(k_fill_multi, dim3(clamp_grid((most + 255) / 256, 4096)), dim3(256), s, f);
   return hipGetLastError();
 }
 

@@ -28,6 +28,21 @@ constexpr int kMergeTile = 256 * 8;   // merged positions per merge tile
 // --- generic -----------------------------------------------------------------
 hipError_t launch_fill64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_fill32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+// up to kFillMax regions of 32- or 64-bit words, each set to its value, in one launch
+constexpr int kFillMax = 12;
+struct FillEntry {
+  void *p;
+  uint64_t n;      // words
+  uint64_t v;
+  uint32_t wide;   // 1: 64-bit words, 0: 32-bit words
+};
+struct FillList {
+  FillEntry e[kFillMax];
+  uint32_t count = 0;
+  void add64(uint64_t *p, uint64_t n, uint64_t v = 0) { e[count++] = {p, n, v, 1}; }
+  void add32(uint32_t *p, uint64_t n, uint32_t v = 0) { e[count++] = {p, n, v, 0}; }
+};
+hipError_t launch_fill_multi(const FillList &f, hipStream_t s);
 // seg[0] = 0, seg[1] = min(*n_dev, n) if n_dev else n
 hipError_t launch_seg1(uint64_t *seg, const uint64_t *n_dev, uint64_t n, hipStream_t s);
 // per-segment tile prefix for up to three tile sizes (null outputs skipped);
