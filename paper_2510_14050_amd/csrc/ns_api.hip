@@ -25,6 +25,11 @@ constexpr int kMaxTickets = 64;
 #define NS_CHUNKED_MIN (1ull << 24)
 #endif
 constexpr uint64_t kChunkedMin = NS_CHUNKED_MIN;
+// Batches of fewer packets run the aggregate pipeline beside the per-window one.
+#ifndef NS_FORK_MAX_PACKETS
+#define NS_FORK_MAX_PACKETS (1ull << 27)
+#endif
+constexpr uint64_t kForkMaxPackets = NS_FORK_MAX_PACKETS;
 constexpr uint64_t kMaxPackets32 = 0xFFFFFFFFull;  // packets per window / matrix < 2^32
 constexpr int kMinSortTile = 256 * 8;
 constexpr int kMinScanTile = 256 * 4;
@@ -482,7 +487,10 @@ struct BatchArgs {
 int enqueue_batch(const BatchArgs &b, Ws &ws, Ws &ws2, hipStream_t s, hipStream_t s2,
                   hipEvent_t fork, hipEvent_t join) {
   HIP_TRY(launch_fill32(ws.at<uint32_t>(ws.L.tickets), kMaxTickets, 0, s));
-  const bool split = b.agg && s2 != s;
+  // Both pipelines are latency-bound on small batches, where running them side
+  // by side fills each other's ramps and tails; on large ones each saturates
+  // HBM alone and sharing the GPU only adds interference.
+  const bool split = b.agg && s2 != s && b.N < kForkMaxPackets;
   if (split) {
     HIP_TRY(hipEventRecord(fork, s));
     HIP_TRY(hipStreamWaitEvent(s2, fork, 0));

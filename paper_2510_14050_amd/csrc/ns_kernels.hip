@@ -1279,7 +1279,9 @@ hipError_t launch_hist_packets(const uint32_t *src, const uint32_t *dst, const u
   static uint64_t cap[64];
   const int d = device_id();
   if (!cap[d]) cap[d] = resident(k_hist<256, true>, 256);
-  NS_LAUNCH((k_hist<256, true>), dim3(clamp_grid(max_tiles, cap[d])), dim3(256), s, src, dst,
+  // at least four tiles per workgroup: each flush of a workgroup's counters
+  // costs one global atomic per bin, so fewer, longer ranges cost fewer atomics
+  NS_LAUNCH((k_hist<256, true>), dim3(clamp_grid((max_tiles + 3) / 4, cap[d])), dim3(256), s, src, dst,
             nullptr, seg_off, tile_off, W, hist);
   return hipGetLastError();
 }
@@ -1290,7 +1292,7 @@ hipError_t launch_hist_items(const uint64_t *items, const uint64_t *seg_off,
   static uint64_t cap[64];
   const int d = device_id();
   if (!cap[d]) cap[d] = resident(k_hist<256, false>, 256);
-  NS_LAUNCH((k_hist<256, false>), dim3(clamp_grid(max_tiles, cap[d])), dim3(256), s, nullptr,
+  NS_LAUNCH((k_hist<256, false>), dim3(clamp_grid((max_tiles + 3) / 4, cap[d])), dim3(256), s, nullptr,
             nullptr, items, seg_off, tile_off, W, hist);
   return hipGetLastError();
 }
