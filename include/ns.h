@@ -115,7 +115,7 @@ int ns_workspace_size(uint64_t max_packets, uint32_t num_windows, uint64_t *byte
 
 /* Build the traffic matrix of one window (Table I caption: A(i,j) counts the
  * packets from i to j). src/dst: n uint32 each. out->keys and out->counts must
- * hold at least n entries (they double as the sort's ping-pong buffers);
+ * hold at least n entries;
  * out->packets is set to n; *out->nnz is written on the device. n = 0 gives an
  * empty matrix. */
 int ns_build_matrix(const uint32_t *src, const uint32_t *dst, uint64_t n, ns_matrix_t *out,

@@ -505,8 +505,10 @@ int enqueue_batch(const BatchArgs &b, Ws &ws, Ws &ws2, hipStream_t s, hipStream_
     o.ukeys = b.agg->keys;
     o.counts = b.agg->counts;
     o.nnz = b.agg->nnz;
-    o.sort_a = b.agg->counts;
-    o.sort_b = b.agg->keys;
+    // sorting in the workspace keeps the run-length pass out of place, so a
+    // tile publishes its counts without first finishing its run-end search
+    o.sort_a = ws2.at<uint64_t>(ws2.L.KA);
+    o.sort_b = ws2.at<uint64_t>(ws2.L.KB);
     int rc = enqueue_packets(ws2, b.sh, b.src, b.dst, seg, 1, b.N, o, sa);
     if (rc) return rc;
     if (split) HIP_TRY(hipEventRecord(join, s2));
@@ -631,8 +633,8 @@ int ns_build_matrix(const uint32_t *src, const uint32_t *dst, uint64_t n, ns_mat
   o.ukeys = out->keys;
   o.counts = out->counts;
   o.nnz = out->nnz;
-  o.sort_a = out->counts;
-  o.sort_b = out->keys;
+  o.sort_a = w.at<uint64_t>(w.L.KA);  // out of place (see the aggregate in enqueue_batch)
+  o.sort_b = w.at<uint64_t>(w.L.KB);
   rc = enqueue_packets(w, sh, src, dst, seg, 1, n, o, s);
   if (rc) return rc;
   out->packets = n;
