@@ -195,6 +195,26 @@ def main():
                "sample": f"{sampled_w} of {W} windows ({sample_pk} packets): per-window "
                          f"8 quantities + aggregate matrix and its 8 quantities, "
                          f"std::sort route, single thread, {c1 - c0:.1f} s"}
+        if sampled_w > 1:
+            # the same sample window-parallel on the host cores (the oracle's C
+            # calls release the GIL, so threads run them side by side)
+            from concurrent.futures import ThreadPoolExecutor
+            T = max(1, min(16, os.cpu_count() or 1))
+            def one(w):
+                a, b = int(off_np[w]), int(off_np[w + 1])
+                return oracle.stats(src[a:b], dst[a:b])
+            p0 = time.perf_counter()
+            with ThreadPoolExecutor(T) as ex:
+                fagg = ex.submit(oracle.stats, src[:sample_pk], dst[:sample_pk])
+                par = list(ex.map(one, range(sampled_w)))
+                par_agg = fagg.result()
+            p1 = time.perf_counter()
+            cpu["parallel"] = {"value": sample_pk / (p1 - p0), "unit": "packets/s", "cores": T,
+                               "kind": "oracle", "sample": f"the same sample, windows and the "
+                               f"aggregate spread over {T} threads, {p1 - p0:.1f} s",
+                               "agrees": bool(np.array_equal(np.array(par), want[:sampled_w])
+                                              and np.array_equal(par_agg, agg_want))}
+            log(f"oracle window-parallel ({T} threads): {sample_pk / (p1 - p0):.4e} packets/s")
         bit_exact = bool(np.array_equal(got[:sampled_w], want[:sampled_w]))
         if sampled_w == W:
             bit_exact = bit_exact and bool(np.array_equal(got_agg, agg_want))
