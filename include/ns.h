@@ -197,6 +197,23 @@ int ns_rolling_compact(const ns_rolling_t *from, const ns_rolling_t *to, void *s
  * word: *status (host) = NS_OK, NS_ERR_UNDERFLOW or NS_ERR_CAPACITY. */
 int ns_device_status(void *stream, int *status);
 
+/* Largest link count max_ij A(i,j) of a matrix: the "maximum link counts"
+ * among the analytics of Sec. IV ("Analytics and Operations"), the maximum
+ * over the matrix's counts. out: device uint64, written with the maximum (0
+ * for an empty matrix). Reads m->counts[0 .. *m->nnz), bounded by
+ * min(m->capacity, m->packets). No workspace. */
+int ns_max_link_packets(const ns_matrix_t *m, uint64_t *out, void *stream);
+
+/* Per-window largest link count of the per-window matrices that
+ * ns_batch_stats wrote into `win` (window w's entries start at offsets[w]).
+ * offsets: device [num_windows+1], the same as given to ns_batch_stats;
+ * total_packets: host bound >= offsets[num_windows] (positions scanned); out:
+ * device [num_windows] uint64 (0 for an empty window). NS_ERR_CAPACITY if
+ * win->capacity < total_packets. */
+int ns_batch_max_link_packets(const ns_batch_matrices_t *win, const uint64_t *offsets,
+                              uint32_t num_windows, uint64_t total_packets, uint64_t *out,
+                              void *stream);
+
 /* Destroys every cached HIP graph (call before freeing buffers a cached graph
  * refers to, or to bound memory). */
 int ns_release_graphs(void);

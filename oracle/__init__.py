@@ -136,3 +136,19 @@ def accumulate(keys_a, counts_a, keys_b, counts_b, sign: int = 1):
     if nnz < 0:
         raise ValueError("subtraction below zero")
     return kc[:nnz].copy(), cc[:nnz].copy()
+
+
+def max_link_packets(src, dst) -> int:
+    """Largest link count max_ij A(i,j) (Sec. IV, "Analytics and Operations":
+    maximum link counts): the largest count of the sorted COO, 0 when empty."""
+    _, counts = build_matrix(src, dst)
+    return int(counts.max()) if counts.size else 0
+
+
+def max_link_packets_windows(src, dst, offsets) -> np.ndarray:
+    """Per-window largest link count, shape (W,)."""
+    o = _u64(offsets)
+    s, d = _u32(src), _u32(dst)
+    return np.array([max_link_packets(s[int(o[w]):int(o[w + 1])], d[int(o[w]):int(o[w + 1])])
+                     for w in range(o.size - 1)], np.uint64)
+

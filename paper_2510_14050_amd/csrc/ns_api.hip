@@ -655,6 +655,25 @@ int ns_stats(const ns_matrix_t *m, ns_stats_t *out, void *ws, uint64_t ws_bytes,
   return enqueue_matrix_stats(w, sh, m, reinterpret_cast<uint64_t *>(out), s);
 }
 
+int ns_max_link_packets(const ns_matrix_t *m, uint64_t *out, void *stream) {
+  if (!m || !out || !m->counts || !m->nnz) return NS_ERR_INVALID_ARG;
+  const uint64_t cap = m->capacity < m->packets ? m->capacity : m->packets;
+  HIP_TRY(launch_max_counts(m->counts, nullptr, m->nnz, 1, cap, out,
+                            static_cast<hipStream_t>(stream)));
+  return NS_OK;
+}
+
+int ns_batch_max_link_packets(const ns_batch_matrices_t *win, const uint64_t *offsets,
+                              uint32_t num_windows, uint64_t total_packets, uint64_t *out,
+                              void *stream) {
+  if (!win || !offsets || !out || !win->counts || !win->nnz) return NS_ERR_INVALID_ARG;
+  if (num_windows == 0) return NS_OK;
+  if (win->capacity < total_packets) return NS_ERR_CAPACITY;
+  HIP_TRY(launch_max_counts(win->counts, offsets, win->nnz, num_windows, total_packets, out,
+                            static_cast<hipStream_t>(stream)));
+  return NS_OK;
+}
+
 int ns_accumulate(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
                   ns_matrix_t *acc_out, void *ws, uint64_t ws_bytes, void *stream) {
   if (!acc_in || !win || !acc_out) return NS_ERR_INVALID_ARG;

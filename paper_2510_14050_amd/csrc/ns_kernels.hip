@@ -944,6 +944,40 @@ __global__ __launch_bounds__(256) void k_runs(RunArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Largest link count per window (Sec. IV, "Analytics and Operations": maximum
+// link counts). Window w's counts sit at [off[w], off[w] + nnz[w]) (the
+// positional layout of the batched per-window matrices); with off == nullptr
+// there is one window at [0, nnz[0]). Each workgroup reduces one contiguous
+// range of positions, window by window, and raises out[w] with one atomic
+// per window it touches; out must start at zero.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_max_counts(const uint64_t *counts, const uint64_t *off,
+                                                    const uint64_t *nnz, uint32_t W,
+                                                    uint64_t total, uint64_t *out) {
+  __shared__ uint64_t s_m[4];
+  const uint64_t per = (total + gridDim.x - 1) / gridDim.x;
+  const uint64_t p0 = (uint64_t)blockIdx.x * per, p1 = min(total, p0 + per);
+  if (p0 >= p1) return;  // the whole workgroup leaves together
+  uint32_t w = off ? find_owner(off, W, p0) : 0;
+  for (; w < W; ++w) {
+    const uint64_t lo = off ? off[w] : 0;
+    if (lo >= p1) break;
+    const uint64_t hi = lo + nnz[w];
+    const uint64_t a = max(lo, p0), b = min(hi, p1);
+    uint64_t m = 0;
+    for (uint64_t p = a + threadIdx.x; p < b; p += 256) m = max(m, counts[p]);
+    m = wave_max(m);
+    if ((threadIdx.x & (kWave - 1)) == 0) s_m[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint64_t v = max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3]));
+      if (v) atomicMax(reinterpret_cast<unsigned long long *>(out + w), (unsigned long long)v);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Per-segment maxima of consecutive-head differences. Each workgroup takes one
 // contiguous range of heads, splits it at segment boundaries (usually none or
 // one), reduces each piece with wave and LDS maxima and issues one 64-bit
@@ -1252,6 +1286,15 @@ hipError_t launch_fill_multi(const FillList &f, hipStream_t s) {
   for (uint32_t q = 0; q < f.count; ++q) most = f.e[q].n > most ? f.e[q].n : most;
   if (most == 0) return hipSuccess;
   NS_LAUNCH(k_fill_multi, dim3(clamp_grid((most + 255) / 256, 4096)), dim3(256), s, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_counts(const uint64_t *counts, const uint64_t *off, const uint64_t *nnz,
+                             uint32_t W, uint64_t total, uint64_t *out, hipStream_t s) {
+  hipError_t e = launch_fill64(out, W, 0, s);
+  if (e != hipSuccess || total == 0) return e;
+  NS_LAUNCH(k_max_counts, dim3(clamp_grid((total + 4095) / 4096, 2048)), dim3(256), s, counts,
+            off, nnz, W, total, out);
   return hipGetLastError();
 }
 

@@ -137,6 +137,11 @@ struct RunArgs {
 hipError_t launch_runs(const ScanShape &sh, int mode, const RunArgs &a, uint64_t max_tiles,
                        hipStream_t s);
 
+// out[w] = max over counts[off[w] .. off[w]+nnz[w]) (0 if empty); off == nullptr:
+// one window at [0, nnz[0]). Positions scanned: [0, total).
+hipError_t launch_max_counts(const uint64_t *counts, const uint64_t *off, const uint64_t *nnz,
+                             uint32_t W, uint64_t total, uint64_t *out, hipStream_t s);
+
 // per segment: stats[w][fa] = max(a[r+1]-a[r]), stats[w][fb] = max(b[r+1]-b[r])
 // over the heads r of segment w (heads [head_off[w], head_off[w+1]))
 hipError_t launch_segmax(const uint64_t *a, const uint64_t *b, const uint64_t *head_off,

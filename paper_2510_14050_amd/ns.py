@@ -63,7 +63,8 @@ class BatchMatricesView(ctypes.Structure):
 
 
 EXPORTS = ("ns_workspace_size", "ns_build_matrix", "ns_accumulate", "ns_stats",
-           "ns_batch_stats", "ns_batch_stats_eager", "ns_rolling_size", "ns_rolling_init",
+           "ns_batch_stats", "ns_batch_stats_eager", "ns_max_link_packets",
+           "ns_batch_max_link_packets", "ns_rolling_size", "ns_rolling_init",
            "ns_rolling_update", "ns_rolling_compact", "ns_device_status", "ns_release_graphs",
            "ns_timing_enable", "ns_timing_reset", "ns_timing_read",
            "ns_error_string", "ns_version")
@@ -99,6 +100,8 @@ def load(path: str = LIB_PATH):
              ctypes.POINTER(Tuning), P, U64, P]
     lib.ns_batch_stats.argtypes = batch
     lib.ns_batch_stats_eager.argtypes = batch
+    lib.ns_max_link_packets.argtypes = [PM, P, P]
+    lib.ns_batch_max_link_packets.argtypes = [ctypes.POINTER(BatchMatricesView), P, U32, U64, P, P]
     PR = ctypes.POINTER(RollingView)
     lib.ns_rolling_size.argtypes = [U64, U64, ctypes.POINTER(U64)]
     lib.ns_rolling_init.argtypes = [PR, P]
@@ -267,6 +270,29 @@ class BatchMatrices:
 
 def tuning(sort_block=0, sort_items=0, digit_bits=0, scan_items=0, chunked_min=0) -> Tuning:
     return Tuning(sort_block, sort_items, digit_bits, scan_items, chunked_min)
+
+
+def max_link_packets(m: Matrix, out, stream=None):
+    """ns_max_link_packets into `out` (int64 cuda tensor, first element)."""
+    v = m.view()
+    assert out.numel() >= 1 and out.dtype.itemsize == 8 and out.is_cuda
+    _check(load().ns_max_link_packets(ctypes.byref(v), _ptr(out), _stream(stream)),
+           "ns_max_link_packets")
+    return out
+
+
+def batch_max_link_packets(win: "BatchMatrices", offsets, out, stream=None):
+    """ns_batch_max_link_packets: out[w] (int64 cuda [W]) = largest link count of
+    window w's matrix in `win` (written by batch_stats with these offsets)."""
+    torch = _torch()
+    assert offsets.dtype == torch.int64 and offsets.is_cuda
+    W = offsets.numel() - 1
+    assert out.numel() >= W and out.dtype.itemsize == 8 and out.is_cuda
+    wv = win.view()
+    N = int(win.capacity)
+    _check(load().ns_batch_max_link_packets(ctypes.byref(wv), _ptr(offsets), W, N, _ptr(out),
+                                            _stream(stream)), "ns_batch_max_link_packets")
+    return out
 
 
 def batch_stats(src, dst, offsets, out, ws: Workspace, agg: Matrix | None = None,

@@ -86,3 +86,17 @@ def test_host_argument_errors(lib):
     aggm = ns.MatrixView(1024, 2048, 3072, 9, 0)
     assert lib.ns_batch_stats(off, off, off, 1, 10, off, ctypes.byref(aggm), None, None, None, ws,
                               1 << 40, None) == -2
+
+
+def test_max_link_argument_errors(lib):
+    assert lib.ns_max_link_packets(None, ctypes.c_void_p(256), None) == -1
+    m = ns.MatrixView(1024, 2048, 3072, 10, 10)
+    assert lib.ns_max_link_packets(ctypes.byref(m), None, None) == -1
+    wv = ns.BatchMatricesView(1024, 2048, 3072, 100)
+    off = ctypes.c_void_p(4096)
+    # zero windows: nothing to do
+    assert lib.ns_batch_max_link_packets(ctypes.byref(wv), off, 0, 100, ctypes.c_void_p(256), None) == 0
+    assert lib.ns_batch_max_link_packets(None, off, 4, 100, ctypes.c_void_p(256), None) == -1
+    assert lib.ns_batch_max_link_packets(ctypes.byref(wv), None, 4, 100, ctypes.c_void_p(256), None) == -1
+    # capacity below the scanned positions
+    assert lib.ns_batch_max_link_packets(ctypes.byref(wv), off, 4, 101, ctypes.c_void_p(256), None) == -2
