@@ -172,6 +172,23 @@ def test_batch_tuning_shapes(gpu, shape):
     check_batch(ns, src, dst, *res)
 
 
+@pytest.mark.parametrize("shape", [(256, 16), (512, 8)])
+def test_batch_layered_tickets(gpu, shape):
+    """Few windows of similar length take radix tickets layer by layer; some
+    windows have one tile fewer (their tickets in the last layer are skipped)
+    and one is empty."""
+    torch, ns = gpu
+    rng = np.random.default_rng(3)
+    tile = shape[0] * shape[1]
+    sizes = [int(x) for x in rng.integers(4 * tile + 1, 5 * tile, 31)] + [0, 4 * tile - 7]
+    say("layered tickets", shape, len(sizes), "windows")
+    src, dst = zipf_packets(44, sum(sizes), pool=5000)
+    t = ns.tuning(sort_block=shape[0], sort_items=shape[1])
+    for graph in (True, False):
+        res = run_batch(torch, ns, src, dst, sizes, tune=t, graph=graph)
+        check_batch(ns, src, dst, *res)
+
+
 CHUNKED_CASES = {
     "ragged_agg": RAGGED,
     "one_window": [300_001],
