@@ -631,6 +631,11 @@ __global__ __launch_bounds__(BLOCK) void k_pass_chunked(PassArgs a, ChunkArgs c)
   }
 }
 
+// LDS index with one pad word after every 8: a thread that owns 8 consecutive
+// positions then reads them without bank conflicts (consecutive lanes land 9
+// words apart instead of 8).
+__device__ __forceinline__ constexpr uint32_t pd(uint32_t j) { return j + (j >> 3); }
+
 // ---------------------------------------------------------------------------
 // First index in (lo, hi] whose key differs from K, given keys[lo] == K in a
 // sorted array (hi if none). The whole calling wave searches together: 64
@@ -684,7 +689,7 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
   constexpr int TILE = BLOCK * ITEMS;
   static_assert(ITEMS <= 32, "head masks are 32-bit");
   static_assert(TILE <= 65536, "tile positions are 16-bit");
-  __shared__ uint64_t s_k[TILE + 1];
+  __shared__ uint64_t s_k[pd(TILE) + 1];  // s_k[pd(1 + i)] = key i of the tile
   __shared__ uint16_t s_hpos[TILE];   // link head positions in the tile
   __shared__ uint16_t s_rpos[TILE];   // row head positions
   __shared__ uint16_t s_rlr[TILE];    // tile-local link rank of each row head
@@ -705,11 +710,11 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
     const uint64_t start = seg_lo + (uint64_t)(t - first) * TILE;
     const uint32_t n = (uint32_t)min((uint64_t)TILE, seg_hi - start);
 
-    for (uint32_t i = tid; i < n; i += BLOCK) s_k[1 + i] = a.keys[start + i];
+    for (uint32_t i = tid; i < n; i += BLOCK) s_k[pd(1 + i)] = a.keys[start + i];
     if (tid == 0) {
       // predecessor of the tile's first key; at a segment start, a value that
       // differs from it in both halves so that position is a link and row head
-      s_k[0] = (start > seg_lo) ? a.keys[start - 1] : (a.keys[start] ^ 0xFFFFFFFF00000001ull);
+      s_k[pd(0)] = (start > seg_lo) ? a.keys[start - 1] : (a.keys[start] ^ 0xFFFFFFFF00000001ull);
     }
     __syncthreads();
 
@@ -719,7 +724,7 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
     for (int k = 0; k < ITEMS; ++k) {
       const uint32_t p = p0 + k;
       if (p < n) {
-        const uint64_t cur = s_k[1 + p], prev = s_k[p];
+        const uint64_t cur = s_k[pd(1 + p)], prev = s_k[pd(p)];
         lmask |= (uint32_t)(cur != prev) << k;
         rmask |= (uint32_t)((cur >> 32) != (prev >> 32)) << k;
       }
@@ -747,7 +752,7 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
     if (tid / kWave == 2) {
       uint64_t e = start + n;
       if (TL > 0 && e < seg_hi) {
-        const uint64_t K = s_k[n];
+        const uint64_t K = s_k[pd(n)];
         if (a.keys[e] == K) e = run_end_wave(a.keys, e, seg_hi, K);
       }
       if ((tid & (kWave - 1)) == 0) s_trail = e;
@@ -809,7 +814,7 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
     const uint64_t wpos = a.win_keys ? seg_lo + L0 - s_base : 0;
     for (uint32_t r = tid; r < TL; r += BLOCK) {
       const uint32_t p = s_hpos[r];
-      const uint64_t K = s_k[1 + p];
+      const uint64_t K = s_k[pd(1 + p)];
       const uint64_t e = (r + 1 < TL) ? start + s_hpos[r + 1] : trail;
       const uint64_t cnt = e - (start + p);
       const uint64_t L = L0 + r;
@@ -846,8 +851,8 @@ __global__ __launch_bounds__(256) void k_runs(RunArgs a) {
   constexpr int BLOCK = 256;
   constexpr int TILE = BLOCK * ITEMS;
   static_assert(TILE <= 65536, "tile positions are 16-bit");
-  __shared__ uint64_t s_g[TILE + 1];   // group key (a 32-bit address; 2^32 marks "none")
-  __shared__ uint32_t s_v[TILE];       // value (< 2^32)
+  __shared__ uint64_t s_g[pd(TILE) + 1];  // s_g[pd(1 + i)]: group key (a 32-bit address; 2^32 marks "none")
+  __shared__ uint32_t s_v[pd(TILE)];      // s_v[pd(i)]: value (< 2^32)
   __shared__ uint16_t s_hp[TILE];      // head local positions
   __shared__ uint32_t s_hv[TILE];      // tile-local exclusive value prefix at head
   __shared__ uint64_t s_tmp[BLOCK / kWave];
@@ -869,16 +874,16 @@ __global__ __launch_bounds__(256) void k_runs(RunArgs a) {
 
     for (uint32_t i = tid; i < n; i += BLOCK) {
       const uint64_t k = a.keys[start + i];
-      s_g[1 + i] = k >> 32;
+      s_g[pd(1 + i)] = k >> 32;
       if (MODE == 0) {
         const uint64_t c = a.counts[start + i];
-        s_v[i] = (uint32_t)c;
+        s_v[pd(i)] = (uint32_t)c;
         if (a.items) a.items[start + i] = (k << 32) | c;
       } else {
-        s_v[i] = (uint32_t)k;
+        s_v[pd(i)] = (uint32_t)k;
       }
     }
-    if (tid == 0) s_g[0] = (start > seg_lo) ? (a.keys[start - 1] >> 32) : ~0ull;
+    if (tid == 0) s_g[pd(0)] = (start > seg_lo) ? (a.keys[start - 1] >> 32) : ~0ull;
     __syncthreads();
 
     uint32_t hmask = 0, vsum = 0;
@@ -887,8 +892,8 @@ __global__ __launch_bounds__(256) void k_runs(RunArgs a) {
     for (int k = 0; k < ITEMS; ++k) {
       const uint32_t p = p0 + k;
       if (p < n) {
-        hmask |= (uint32_t)(s_g[1 + p] != s_g[p]) << k;
-        vsum += s_v[p];
+        hmask |= (uint32_t)(s_g[pd(1 + p)] != s_g[pd(p)]) << k;
+        vsum += s_v[pd(p)];
       }
     }
     uint64_t tot;
@@ -905,7 +910,7 @@ __global__ __launch_bounds__(256) void k_runs(RunArgs a) {
           s_hv[jh] = run;
           ++jh;
         }
-        if (p < n) run += s_v[p];
+        if (p < n) run += s_v[pd(p)];
       }
     }
     if (tid < 2) lb_store(a.lb + 2ull * t + tid, (t == 0 ? kLbInc : kLbAgg) | (tid == 0 ? TH : TV));
