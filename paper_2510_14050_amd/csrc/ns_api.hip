@@ -487,6 +487,28 @@ struct BatchArgs {
 int enqueue_batch(const BatchArgs &b, Ws &ws, Ws &ws2, hipStream_t s, hipStream_t s2,
                   hipEvent_t fork, hipEvent_t join) {
   HIP_TRY(launch_fill32(ws.at<uint32_t>(ws.L.tickets), kMaxTickets, 0, s));
+  if (b.agg && b.W == 1) {
+    // one window: its matrix is the aggregate, so one pipeline writes both
+    // (and the window's quantities are copied to the aggregate's)
+    PacketOut o{};
+    o.stats = reinterpret_cast<uint64_t *>(b.out);
+    o.ukeys = b.agg->keys;
+    o.counts = b.agg->counts;
+    o.nnz = b.agg->nnz;
+    o.sort_a = ws.at<uint64_t>(ws.L.KA);
+    o.sort_b = ws.at<uint64_t>(ws.L.KB);
+    if (b.win) {
+      o.win_keys = b.win->keys;
+      o.win_counts = b.win->counts;
+      o.win_nnz = b.win->nnz;
+    }
+    int rc = enqueue_packets(ws, b.sh, b.src, b.dst, b.offsets, 1, b.N, o, s);
+    if (rc) return rc;
+    if (b.agg_stats)
+      HIP_TRY(launch_copy64(reinterpret_cast<uint64_t *>(b.agg_stats),
+                            reinterpret_cast<const uint64_t *>(b.out), 8, s));
+    return NS_OK;
+  }
   // Both pipelines are latency-bound on small batches, where running them side
   // by side fills each other's ramps and tails; on large ones each saturates
   // HBM alone and sharing the GPU only adds interference.

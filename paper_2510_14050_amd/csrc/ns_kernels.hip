@@ -41,6 +41,12 @@ __global__ void k_fill32(uint32_t *p, uint64_t n, uint32_t v) {
     p[i] = v;
 }
 
+__global__ void k_copy64(uint64_t *dst, const uint64_t *src, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 // Several fills in one launch (each region written with its own value).
 __global__ void k_fill_multi(FillList f) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -1283,6 +1289,12 @@ hipError_t launch_fill64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const uint32_t g = clamp_grid((n + 255) / 256, 4096);
   NS_LAUNCH(k_fill64, dim3(g), dim3(256), s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy64(uint64_t *dst, const uint64_t *src, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  NS_LAUNCH(k_copy64, dim3(clamp_grid((n + 255) / 256, 4096)), dim3(256), s, dst, src, n);
   return hipGetLastError();
 }
 

@@ -43,6 +43,7 @@ struct FillList {
   void add32(uint32_t *p, uint64_t n, uint32_t v = 0) { e[count++] = {p, n, v, 0}; }
 };
 hipError_t launch_fill_multi(const FillList &f, hipStream_t s);
+hipError_t launch_copy64(uint64_t *dst, const uint64_t *src, uint64_t n, hipStream_t s);
 // seg[0] = 0, seg[1] = min(*n_dev, n) if n_dev else n
 hipError_t launch_seg1(uint64_t *seg, const uint64_t *n_dev, uint64_t n, hipStream_t s);
 // per-segment tile prefix for up to three tile sizes (null outputs skipped);
