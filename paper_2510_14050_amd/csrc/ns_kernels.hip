@@ -15,6 +15,10 @@
 #ifndef NS_LAYER_MAX_W
 #define NS_LAYER_MAX_W 256  // most segments for layered ticket order
 #endif
+#ifndef NS_HIST_BLOCK
+#define NS_HIST_BLOCK 512  // threads of a histogram workgroup
+#endif
+constexpr int kHistBlock = NS_HIST_BLOCK;
 #ifndef NS_CHUNKS_PER_CU
 #define NS_CHUNKS_PER_CU 2  // chunks of a large single-segment pass per CU
 #endif
@@ -1338,10 +1342,10 @@ hipError_t launch_hist_packets(const uint32_t *src, const uint32_t *dst, const u
                                uint32_t *hist, hipStream_t s) {
   static uint64_t cap[64];
   const int d = device_id();
-  if (!cap[d]) cap[d] = resident(k_hist<256, true>, 256);
+  if (!cap[d]) cap[d] = resident(k_hist<kHistBlock, true>, kHistBlock);
   // at least four tiles per workgroup: each flush of a workgroup's counters
   // costs one global atomic per bin, so fewer, longer ranges cost fewer atomics
-  NS_LAUNCH((k_hist<256, true>), dim3(clamp_grid((max_tiles + 3) / 4, cap[d])), dim3(256), s, src, dst,
+  NS_LAUNCH((k_hist<kHistBlock, true>), dim3(clamp_grid((max_tiles + 3) / 4, cap[d])), dim3(kHistBlock), s, src, dst,
             nullptr, seg_off, tile_off, W, hist);
   return hipGetLastError();
 }
@@ -1351,8 +1355,8 @@ hipError_t launch_hist_items(const uint64_t *items, const uint64_t *seg_off,
                              uint32_t *hist, hipStream_t s) {
   static uint64_t cap[64];
   const int d = device_id();
-  if (!cap[d]) cap[d] = resident(k_hist<256, false>, 256);
-  NS_LAUNCH((k_hist<256, false>), dim3(clamp_grid((max_tiles + 3) / 4, cap[d])), dim3(256), s, nullptr,
+  if (!cap[d]) cap[d] = resident(k_hist<kHistBlock, false>, kHistBlock);
+  NS_LAUNCH((k_hist<kHistBlock, false>), dim3(clamp_grid((max_tiles + 3) / 4, cap[d])), dim3(kHistBlock), s, nullptr,
             nullptr, items, seg_off, tile_off, W, hist);
   return hipGetLastError();
 }
