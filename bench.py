@@ -44,6 +44,8 @@ def parse():
                    help="serving leg: arrivals (the first --serve-warm are warm-up); 0 = skip")
     p.add_argument("--serve-warm", type=int, default=1024)
     p.add_argument("--serve-rate", type=float, default=2000.0)
+    p.add_argument("--no-analysis", action="store_true",
+                   help="skip timing ns_stats on the pre-built aggregate")
     p.add_argument("--copy-calibration-mib", type=int, default=0,
                    help="first run a plain device copy of this many MiB (3 times), whose "
                         "memory counters calibrate the profiler's byte counts")
@@ -135,21 +137,23 @@ def main():
 
     # --- analysis only: the eight quantities of the pre-built aggregate matrix
     # (construction excluded, the shape of the paper's timed analysis) ---
-    an_st = torch.zeros(8, dtype=torch.int64, device=dev)
-    for _ in range(2):
-        ns.stats(agg, an_st, ws)
-    torch.cuda.synchronize()
-    reps = max(3, min(50, args.steps))
-    a0 = time.perf_counter()
-    for _ in range(reps):
-        ns.stats(agg, an_st, ws)
-    torch.cuda.synchronize()
-    an_ms = (time.perf_counter() - a0) * 1e3 / reps
-    analysis = {"ms": round(an_ms, 4), "matrix_nnz": agg_nnz, "packets": N,
-                "packets_per_s": N / (an_ms * 1e-3),
-                "same_as_batched": bool(np.array_equal(ns.stats_numpy(an_st), got_agg)),
-                "what": "ns_stats on the pre-built aggregate matrix (construction excluded)"}
-    log(f"analysis of the pre-built aggregate: {an_ms:.3f} ms ({agg_nnz} links)")
+    analysis = None
+    if not args.no_analysis:
+        an_st = torch.zeros(8, dtype=torch.int64, device=dev)
+        for _ in range(2):
+            ns.stats(agg, an_st, ws)
+        torch.cuda.synchronize()
+        reps = max(3, min(50, args.steps))
+        a0 = time.perf_counter()
+        for _ in range(reps):
+            ns.stats(agg, an_st, ws)
+        torch.cuda.synchronize()
+        an_ms = (time.perf_counter() - a0) * 1e3 / reps
+        analysis = {"ms": round(an_ms, 4), "matrix_nnz": agg_nnz, "packets": N,
+                    "packets_per_s": N / (an_ms * 1e-3),
+                    "same_as_batched": bool(np.array_equal(ns.stats_numpy(an_st), got_agg)),
+                    "what": "ns_stats on the pre-built aggregate matrix (construction excluded)"}
+        log(f"analysis of the pre-built aggregate: {an_ms:.3f} ms ({agg_nnz} links)")
 
     # --- plain per-window path ---
     plain = None
