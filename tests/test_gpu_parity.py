@@ -189,6 +189,23 @@ def test_batch_layered_tickets(gpu, shape):
         check_batch(ns, src, dst, *res)
 
 
+@pytest.mark.parametrize("graph", [True, False], ids=["graph", "eager"])
+@pytest.mark.parametrize("W", [2, 3, 5, 64, 127, 128, 129, 200])
+def test_batch_aggregate_window_counts(gpu, W, graph):
+    """The aggregate and every window over a range of window counts (odd,
+    powers of two, either side of 128), with and without the per-window
+    matrices requested, with an empty window mixed in."""
+    torch, ns = gpu
+    rng = np.random.default_rng(W)
+    sizes = [int(x) for x in rng.integers(0, 3000, W)]
+    sizes[W // 2] = 0
+    say("aggregate, windows:", W, "graph" if graph else "eager")
+    src, dst = zipf_packets(500 + W, sum(sizes), pool=700)
+    for win in (True, False):
+        res = run_batch(torch, ns, src, dst, sizes, graph=graph, win=win)
+        check_batch(ns, src, dst, *res)
+
+
 CHUNKED_CASES = {
     "ragged_agg": RAGGED,
     "one_window": [300_001],
