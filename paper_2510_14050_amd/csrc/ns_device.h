@@ -29,25 +29,6 @@ __device__ __forceinline__ uint64_t lb_load(const uint64_t *p) {
   return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Exclusive prefix of channel `chan` for tile t: sum of the aggregates of tiles
-// first..t-1, walking back until an inclusive prefix is found. `stride` is the
-// number of channels per tile.
-__device__ __forceinline__ uint64_t lb_walk(const uint64_t *lb, uint32_t stride, uint32_t chan,
-                                            uint32_t t, uint32_t first) {
-  uint64_t excl = 0;
-  for (int64_t j = (int64_t)t - 1; j >= (int64_t)first; --j) {
-    const uint64_t *p = lb + (uint64_t)j * stride + chan;
-    uint64_t v = lb_load(p);
-    while ((v >> 62) == 0) {
-      __builtin_amdgcn_s_sleep(1);
-      v = lb_load(p);
-    }
-    excl += v & kLbVal;
-    if ((v >> 62) == 2) break;
-  }
-  return excl;
-}
-
 // ---------------------------------------------------------------------------
 // wave / block helpers
 // ---------------------------------------------------------------------------
@@ -113,8 +94,11 @@ __device__ __forceinline__ uint32_t find_owner(const uint64_t *off, uint32_t W, 
   return lo;
 }
 
-// Same result as lb_walk, with up to P predecessor words in flight per round
-// trip (each thread issues the loads of tiles j, j-1, ..., j-P+1 together).
+// Exclusive prefix of channel `chan` for tile t: the sum of the values of
+// tiles t-1, t-2, ... back to and including the nearest one that published
+// an inclusive prefix (tile `first` always does). `stride` is the number of
+// channels per tile. Up to P predecessor words are in flight per round trip
+// (each thread issues the loads of tiles j, j-1, ..., j-P+1 together).
 template <int P>
 __device__ __forceinline__ uint64_t lb_walkn(const uint64_t *lb, uint32_t stride, uint32_t chan,
                                              uint32_t t, uint32_t first) {

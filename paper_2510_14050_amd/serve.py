@@ -16,7 +16,8 @@ over windows max(0, k-ring+1)..k by arrival sequence, whatever the batching.
 
 Latency of an arrival = time its two result rows are on the host minus its
 arrival time. All computation goes through the libns C ABI
-(ns_batch_stats_eager, ns_accumulate, ns_stats); this module only moves bytes,
+(ns_batch_stats_eager, ns_rolling_update, ns_rolling_compact, and in merge mode
+ns_accumulate and ns_stats); this module only moves bytes,
 keeps lifetimes and keeps time.
 """
 from __future__ import annotations
