@@ -54,6 +54,16 @@ __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
   return x;
 }
 
+__device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t x) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
 __device__ __forceinline__ uint64_t wave_max(uint64_t x) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) {
@@ -83,15 +93,37 @@ __device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *s_tmp,
   return pre + x - v;
 }
 
-// index of the segment that owns tile t: the last w with tile_off[w] <= t
-// (empty segments own no tiles, so this is never an empty one)
+// Index of the segment that owns tile t: the last w with off[w] <= t (empty
+// segments own no tiles, so this is never an empty one). Binary search; with t
+// uniform (in scalar registers) its loads are scalar and mostly hit the scalar
+// cache.
 __device__ __forceinline__ uint32_t find_owner(const uint64_t *off, uint32_t W, uint64_t t) {
-  uint32_t lo = 0, hi = W;  // answer in [0, W)
+  uint32_t lo = 0, hi = W;  // answer in [lo, hi)
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
     if (off[mid] <= t) lo = mid; else hi = mid;
   }
   return lo;
+}
+
+// The same owner, searched by a whole wave (all 64 lanes active, t uniform)
+// where t is not known to be uniform: each round probes 64 evenly spaced
+// entries of the remaining range, so W segments take ceil(log64 W) dependent
+// loads instead of log2 W. off is nondecreasing, so the probes with
+// off[p] <= t form a prefix of the lanes (lane 0, at the low end, always
+// belongs to it).
+__device__ __forceinline__ uint32_t find_owner_wave(const uint64_t *off, uint32_t W, uint64_t t) {
+  const uint64_t lane = threadIdx.x & (kWave - 1);
+  uint64_t lo = 0, hi = W;  // answer in [lo, hi), off[lo] <= t
+  while (hi - lo > 1) {
+    const uint64_t step = (hi - lo + kWave - 1) / kWave;
+    const uint64_t p = lo + step * lane;
+    const uint64_t m = ballot64(p < hi && off[p] <= t);
+    const uint64_t f = 63 - __clzll((long long)m);  // highest probe at or below t
+    hi = min(lo + step * (f + 1), hi);
+    lo += step * f;
+  }
+  return (uint32_t)lo;
 }
 
 // Exclusive prefix of channel `chan` for tile t: the sum of the values of

@@ -162,9 +162,10 @@ __global__ __launch_bounds__(BLOCK) void k_hist(const uint32_t *__restrict__ src
 #pragma unroll
     for (int q = 0; q < 4; ++q) atomicAdd(&s_h[((d0 + q) * kBins + ((v >> (8 * q)) & 255)) * C + cp], 1u);
   };
-  uint32_t cur = t0 < t1 ? find_owner(tile_off, W, t0) : 0;
+  uint32_t cur = t0 < t1 ? find_owner_wave(tile_off, W, t0) : 0;
   for (uint64_t t = t0; t < t1; ++t) {
-    const uint32_t w = find_owner(tile_off, W, t);
+    uint32_t w = cur;  // tiles come in order: step over finished (and empty) segments
+    while (tile_off[w + 1] <= t) ++w;
     if (w != cur) {  // uniform: every thread sees the same tile
       __syncthreads();
       flush(cur);
@@ -235,32 +236,57 @@ __global__ __launch_bounds__(256) void k_hist_scan(const uint32_t *hist, uint32_
 // segment. Keys are scattered into LDS in digit order and written out from
 // there, so consecutive threads write consecutive addresses within a digit.
 // ---------------------------------------------------------------------------
+// Bit B of d spread over all 32 bits (all ones where it is set). Written as
+// v_bfe_i32 so that the compiler keeps one instruction per bit instead of
+// rebuilding the mask from shifts.
+template <int B>
+__device__ __forceinline__ uint32_t bit_mask(uint32_t d) {
+  uint32_t e;
+  asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(e) : "v"(d), "i"(B));
+  return e;
+}
+
+// One digit bit of the peer search: keep the lanes whose bit B equals this
+// lane's. v_bitop3 truth table 0x90 (index p*4 + m*2 + e) = p & ~(m ^ e), so
+// each 32-lane half costs one instruction.
+template <int B>
+__device__ __forceinline__ void peer_bit(uint32_t d, uint32_t &plo, uint32_t &phi) {
+  const uint32_t e = bit_mask<B>(d);
+  const uint64_t m = ballot64(e != 0);
+  plo = __builtin_amdgcn_bitop3_b32(plo, (uint32_t)m, e, 0x90);
+  phi = __builtin_amdgcn_bitop3_b32(phi, (uint32_t)(m >> 32), e, 0x90);
+}
+
 // Stable rank of each key among the wave's keys with the same digit, in
 // (item, lane) order = original order; wcnt[d] holds the wave's running count
-// of digit d (digit kBins marks a missing key). The peer mask is built on
-// 32-bit halves: for each digit bit, the ballot m is kept where this lane's bit
-// is set and its complement where it is clear. The lowest lane of each group
-// of equal digits updates the counter, so a hot digit costs one LDS update per
-// wave, not per lane.
-template <int ITEMS>
+// of digit d. The peer mask (lanes holding the same digit) is the intersection
+// over the 8 digit bits of the ballot where this lane's bit is set and its
+// complement where it is clear. The lowest lane of each group of equal digits
+// updates the counter, so a hot digit costs one LDS update per wave, not per
+// lane. FULL: every lane holds a key; otherwise digit kBins marks a missing
+// key, which is left out of every peer mask and not ranked.
+template <int ITEMS, bool FULL>
 __device__ __forceinline__ void wave_rank(const uint32_t (&dig)[ITEMS], uint32_t (&rank)[ITEMS],
                                           uint32_t *wcnt) {
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     const uint32_t d = dig[k];
-    const bool valid = d < kBins;
-    const uint64_t vm = ballot64(valid);
-    uint32_t plo = (uint32_t)vm, phi = (uint32_t)(vm >> 32);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      // all ones where this lane's bit b is set, zero where it is clear
-      const uint32_t ext = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
-      const uint64_t m = ballot64(ext != 0);
-      plo &= ~((uint32_t)m ^ ext);
-      phi &= ~((uint32_t)(m >> 32) ^ ext);
+    uint32_t plo = ~0u, phi = ~0u;
+    if (!FULL) {
+      const uint64_t vm = ballot64(d < kBins);
+      plo = (uint32_t)vm;
+      phi = (uint32_t)(vm >> 32);
     }
+    peer_bit<0>(d, plo, phi);
+    peer_bit<1>(d, plo, phi);
+    peer_bit<2>(d, plo, phi);
+    peer_bit<3>(d, plo, phi);
+    peer_bit<4>(d, plo, phi);
+    peer_bit<5>(d, plo, phi);
+    peer_bit<6>(d, plo, phi);
+    peer_bit<7>(d, plo, phi);
     const uint64_t peers = ((uint64_t)phi << 32) | plo;
-    if (valid) {
+    if (FULL || d < kBins) {
       const uint32_t below = count_below(peers);
       const uint32_t old = wcnt[d];
       rank[k] = old + below;
@@ -269,16 +295,96 @@ __device__ __forceinline__ void wave_rank(const uint32_t (&dig)[ITEMS], uint32_t
   }
 }
 
-// Exclusive scan of the 256 digit totals of a tile, by one wave (4 per lane).
-__device__ __forceinline__ void local_starts(const uint32_t *tot, uint32_t *lstart, int lane) {
-  const uint32_t v0 = tot[lane * 4], v1 = tot[lane * 4 + 1], v2 = tot[lane * 4 + 2],
-                 v3 = tot[lane * 4 + 3];
-  const uint64_t mine = (uint64_t)v0 + v1 + v2 + v3;
-  const uint32_t x = (uint32_t)(wave_incl_scan(mine) - mine);
-  lstart[lane * 4] = x;
-  lstart[lane * 4 + 1] = x + v0;
-  lstart[lane * 4 + 2] = x + v0 + v1;
-  lstart[lane * 4 + 3] = x + v0 + v1 + v2;
+// Digits of a wave-striped tile (kBins for positions at or past n) and their
+// stable ranks within the wave.
+template <int ITEMS, bool FULL>
+__device__ __forceinline__ void rank_tile(const uint64_t (&key)[ITEMS], uint32_t shift, uint32_t n,
+                                          uint32_t wbase, int lane, uint32_t (&dig)[ITEMS],
+                                          uint32_t (&rank)[ITEMS], uint32_t *wcnt) {
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const uint32_t d = (uint32_t)(key[k] >> shift) & 255u;
+    dig[k] = (FULL || wbase + k * kWave + lane < n) ? d : kBins;
+  }
+  wave_rank<ITEMS, FULL>(dig, rank, wcnt);
+}
+
+// Tile positions from the per-wave digit counts, on all BLOCK threads between
+// two barriers of the caller. Thread d < kBins sums digit d over the waves
+// (*tot, handed to publish() at once for the look-back), the 256 totals are
+// scanned across the first four waves, and s_wcnt[q][d] becomes the tile
+// position of wave q's first key with digit d, *lstart that of the tile's
+// first key with digit d. Ends with a barrier.
+template <int NW, typename Publish>
+__device__ __forceinline__ void tile_offsets(uint32_t (*s_wcnt)[kBins], uint32_t *s_part, int tid,
+                                             uint32_t *tot, uint32_t *lstart, Publish publish) {
+  const int lane = tid & (kWave - 1), wv = tid / kWave;
+  uint32_t run[NW];
+  uint32_t sum = 0, incl = 0;
+  if (tid < kBins) {
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      run[q] = sum;
+      sum += s_wcnt[q][tid];
+    }
+    publish(sum);
+    incl = wave_incl_scan32(sum);
+    if (lane == kWave - 1) s_part[wv] = incl;
+  }
+  __syncthreads();
+  if (tid < kBins) {
+    uint32_t base = incl - sum;
+#pragma unroll
+    for (int q = 0; q < kBins / kWave; ++q) base += q < wv ? s_part[q] : 0u;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) s_wcnt[q][tid] = base + run[q];
+    *tot = sum;
+    *lstart = base;
+  }
+  __syncthreads();
+}
+
+// Keys into the tile's LDS buffer in digit order.
+template <int ITEMS, bool FULL>
+__device__ __forceinline__ void place_tile(const uint64_t (&key)[ITEMS], const uint32_t (&dig)[ITEMS],
+                                           const uint32_t (&rank)[ITEMS], const uint32_t *wpos,
+                                           uint64_t *s_keys) {
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const uint32_t d = dig[k];
+    if (FULL || d < kBins) s_keys[wpos[d] + rank[k]] = key[k];
+  }
+}
+
+// The tile's keys from LDS (digit order) to their output positions:
+// out[s_gdel[d] + i] for the key at LDS position i with digit d. A full tile
+// goes in unrolled batches so that each batch's LDS reads are in flight
+// together; a partial tile loops.
+template <int BLOCK, int ITEMS>
+__device__ __forceinline__ void write_tile(const uint64_t *s_keys, const uint64_t *s_gdel,
+                                           uint32_t n, uint32_t shift, int tid, uint64_t *out) {
+  if (n == (uint32_t)(BLOCK * ITEMS)) {
+    // opaque copy of the thread index: keeps the compiler from hoisting one
+    // 64-bit address per item out of the tile loop (registers it lacks)
+    uint32_t tb = tid;
+    asm volatile("" : "+v"(tb));
+    constexpr int R = ITEMS < 8 ? ITEMS : 8;
+#pragma unroll
+    for (int q0 = 0; q0 < ITEMS; q0 += R) {
+      uint64_t x[R], g[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) x[q] = s_keys[tb + (q0 + q) * BLOCK];
+#pragma unroll
+      for (int q = 0; q < R; ++q) g[q] = s_gdel[(uint32_t)(x[q] >> shift) & 255u] + tb;
+#pragma unroll
+      for (int q = 0; q < R; ++q) out[g[q] + (q0 + q) * BLOCK] = x[q];
+    }
+  } else {
+    for (uint32_t i = tid; i < n; i += BLOCK) {
+      const uint64_t x = s_keys[i];
+      out[s_gdel[(uint32_t)(x >> shift) & 255u] + i] = x;
+    }
+  }
 }
 
 // Next tile of a radix pass. With several segments of similar length, tickets
@@ -287,10 +393,14 @@ __device__ __forceinline__ void local_starts(const uint32_t *tot, uint32_t *lsta
 // smaller and has usually finished. Otherwise tickets follow tile order. Either
 // way every predecessor holds a smaller ticket, so look-back waits always end.
 // Returns ~0u when the pass is exhausted; *seg receives the tile's segment.
+// Called by a whole wave; every lane returns the same ticket.
 __device__ __forceinline__ uint32_t pass_ticket(const PassArgs &a, uint64_t layers,
                                                 uint64_t tickets, uint32_t *seg) {
+  const int lane = threadIdx.x & (kWave - 1);
   for (;;) {
-    const uint64_t k = atomicAdd(a.ticket, 1u);
+    uint32_t k0 = 0;
+    if (lane == 0) k0 = atomicAdd(a.ticket, 1u);
+    const uint64_t k = (uint32_t)__builtin_amdgcn_readfirstlane(k0);
     if (k >= tickets) return 0xFFFFFFFFu;
     if (!layers) {
       *seg = find_owner(a.tile_off, a.W, k);
@@ -332,15 +442,14 @@ __device__ __forceinline__ void pass_load(const PassArgs &a, uint64_t start, uin
 }
 
 template <int BLOCK, int ITEMS, bool PACKETS>
-__global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_pass(PassArgs a) {
   constexpr int TILE = BLOCK * ITEMS;
   constexpr int NW = BLOCK / kWave;
   static_assert(BLOCK >= kBins, "one thread per digit");
   __shared__ uint64_t s_keys[TILE];
   __shared__ uint32_t s_wcnt[NW][kBins];
-  __shared__ uint32_t s_tot[kBins];
-  __shared__ uint32_t s_lstart[kBins];
-  __shared__ uint64_t s_gbase[kBins];
+  __shared__ uint32_t s_part[kBins / kWave];
+  __shared__ uint64_t s_gdel[kBins];  // output position of digit d's keys minus their tile position
   __shared__ uint32_t s_tile, s_seg;
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
@@ -356,10 +465,13 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
   const bool pipe = a.W > 1;
 
   for (int i = tid; i < NW * kBins; i += BLOCK) (&s_wcnt[0][0])[i] = 0;
-  if (tid == 0) {
+  if (tid < kWave) {
     uint32_t w = 0;
-    s_tile = pass_ticket(a, layers, tickets, &w);
-    s_seg = w;
+    const uint32_t tk = pass_ticket(a, layers, tickets, &w);
+    if (tid == 0) {
+      s_tile = tk;
+      s_seg = w;
+    }
   }
   __syncthreads();
   uint32_t t = s_tile, w = s_seg;
@@ -377,38 +489,25 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
   while (t != 0xFFFFFFFFu) {
     uint32_t dig[ITEMS];
     uint32_t rank[ITEMS];
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint32_t li = wbase + k * kWave + lane;
-      dig[k] = li < n ? (uint32_t)(key[k] >> shift) & 255u : kBins;
-    }
-    wave_rank<ITEMS>(dig, rank, s_wcnt[wv]);
+    const bool full = n == TILE;
+    if (full) rank_tile<ITEMS, true>(key, shift, n, wbase, lane, dig, rank, s_wcnt[wv]);
+    else rank_tile<ITEMS, false>(key, shift, n, wbase, lane, dig, rank, s_wcnt[wv]);
     __syncthreads();
-    if (tid < kBins) {
-      uint32_t sum = 0;
-#pragma unroll
-      for (int q = 0; q < NW; ++q) {
-        const uint32_t c = s_wcnt[q][tid];
-        s_wcnt[q][tid] = sum;
-        sum += c;
-      }
-      s_tot[tid] = sum;
-      // publish this tile's digit counts as early as possible
+    uint32_t tot = 0, lstart = 0;
+    // publish this tile's digit counts as early as possible
+    tile_offsets<NW>(s_wcnt, s_part, tid, &tot, &lstart, [&](uint32_t sum) {
       lb_store(a.lb + (uint64_t)t * kBins + tid, (t == first ? kLbInc : kLbAgg) | sum);
-    }
-    __syncthreads();
-    if (tid < kWave) local_starts(s_tot, s_lstart, tid);
-    __syncthreads();
+    });
     // local counting sort of the tile into LDS; the key registers are free after
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint32_t d = dig[k];
-      if (d < kBins) s_keys[s_lstart[d] + s_wcnt[wv][d] + rank[k]] = key[k];
-    }
-    if (pipe && tid == 0) {
+    if (full) place_tile<ITEMS, true>(key, dig, rank, s_wcnt[wv], s_keys);
+    else place_tile<ITEMS, false>(key, dig, rank, s_wcnt[wv], s_keys);
+    if (pipe && tid < kWave) {
       uint32_t nw = 0;
-      s_tile = pass_ticket(a, layers, tickets, &nw);
-      s_seg = nw;
+      const uint32_t tk = pass_ticket(a, layers, tickets, &nw);
+      if (tid == 0) {
+        s_tile = tk;
+        s_seg = nw;
+      }
     }
     __syncthreads();
     for (int i = tid; i < NW * kBins; i += BLOCK) (&s_wcnt[0][0])[i] = 0;
@@ -430,21 +529,20 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
       uint64_t excl = 0;
       if (t != first) {
         excl = lb_walkn<NS_LB_DEPTH>(a.lb, kBins, tid, t, first);
-        lb_store(a.lb + (uint64_t)t * kBins + tid, kLbInc | (excl + s_tot[tid]));
+        lb_store(a.lb + (uint64_t)t * kBins + tid, kLbInc | (excl + tot));
       }
-      s_gbase[tid] = seg_lo + a.base[(uint64_t)w * a.base_stride + tid] + excl;
+      s_gdel[tid] = seg_lo + a.base[(uint64_t)w * a.base_stride + tid] + excl - lstart;
       a.lb_next[(uint64_t)t * kBins + tid] = 0;
     }
     __syncthreads();
-    for (uint32_t i = tid; i < n; i += BLOCK) {
-      const uint64_t x = s_keys[i];
-      const uint32_t d = (uint32_t)(x >> shift) & 255u;
-      a.out[s_gbase[d] + (i - s_lstart[d])] = x;
-    }
-    if (!pipe && tid == 0) {
+    write_tile<BLOCK, ITEMS>(s_keys, s_gdel, n, shift, tid, a.out);
+    if (!pipe && tid < kWave) {
       uint32_t nw = 0;
-      s_tile = pass_ticket(a, layers, tickets, &nw);
-      s_seg = nw;
+      const uint32_t tk = pass_ticket(a, layers, tickets, &nw);
+      if (tid == 0) {
+        s_tile = tk;
+        s_seg = nw;
+      }
     }
     __syncthreads();
     if (!pipe) {
@@ -554,15 +652,14 @@ __global__ __launch_bounds__(256) void k_chunk_scan(ChunkArgs c) {
 }
 
 template <int BLOCK, int ITEMS, bool PACKETS>
-__global__ __launch_bounds__(BLOCK) void k_pass_chunked(PassArgs a, ChunkArgs c) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_pass_chunked(PassArgs a, ChunkArgs c) {
   constexpr int TILE = BLOCK * ITEMS;
   constexpr int NW = BLOCK / kWave;
   static_assert(BLOCK >= kBins, "one thread per digit");
   __shared__ uint64_t s_keys[TILE];
   __shared__ uint32_t s_wcnt[NW][kBins];
-  __shared__ uint32_t s_tot[kBins];
-  __shared__ uint32_t s_lstart[kBins];
-  __shared__ uint64_t s_gbase[kBins];
+  __shared__ uint32_t s_part[kBins / kWave];
+  __shared__ uint64_t s_gdel[kBins];  // output position of digit d's keys minus their tile position
   __shared__ uint32_t s_chunk;
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
@@ -585,7 +682,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass_chunked(PassArgs a, ChunkArgs c)
     const uint32_t ch = s_chunk;
     if (ch >= c.chunks) break;
     const uint64_t t0 = min(tiles, (uint64_t)ch * per), t1 = min(tiles, t0 + per);
-    if (tid < kBins) s_gbase[tid] = s_dbase[tid] + c.prefix[(uint64_t)ch * kBins + tid];
+    // thread d < kBins: output position of the chunk's next key with digit d
+    uint64_t gbase = tid < kBins ? s_dbase[tid] + c.prefix[(uint64_t)ch * kBins + tid] : 0;
     uint64_t key[ITEMS];
     uint32_t n = 0;
     if (t0 < t1) {
@@ -596,31 +694,15 @@ __global__ __launch_bounds__(BLOCK) void k_pass_chunked(PassArgs a, ChunkArgs c)
     for (uint64_t t = t0; t < t1; ++t) {
       uint32_t dig[ITEMS];
       uint32_t rank[ITEMS];
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t li = wbase + k * kWave + lane;
-        dig[k] = li < n ? (uint32_t)(key[k] >> shift) & 255u : kBins;
-      }
-      wave_rank<ITEMS>(dig, rank, s_wcnt[wv]);
+      const bool full = n == TILE;
+      if (full) rank_tile<ITEMS, true>(key, shift, n, wbase, lane, dig, rank, s_wcnt[wv]);
+      else rank_tile<ITEMS, false>(key, shift, n, wbase, lane, dig, rank, s_wcnt[wv]);
       __syncthreads();
-      if (tid < kBins) {
-        uint32_t sum = 0;
-#pragma unroll
-        for (int q = 0; q < NW; ++q) {
-          const uint32_t v = s_wcnt[q][tid];
-          s_wcnt[q][tid] = sum;
-          sum += v;
-        }
-        s_tot[tid] = sum;
-      }
-      __syncthreads();
-      if (tid < kWave) local_starts(s_tot, s_lstart, tid);
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t d = dig[k];
-        if (d < kBins) s_keys[s_lstart[d] + s_wcnt[wv][d] + rank[k]] = key[k];
-      }
+      uint32_t tot = 0, lstart = 0;
+      tile_offsets<NW>(s_wcnt, s_part, tid, &tot, &lstart, [](uint32_t) {});
+      if (tid < kBins) s_gdel[tid] = gbase - lstart;
+      if (full) place_tile<ITEMS, true>(key, dig, rank, s_wcnt[wv], s_keys);
+      else place_tile<ITEMS, false>(key, dig, rank, s_wcnt[wv], s_keys);
       __syncthreads();
       for (int i = tid; i < NW * kBins; i += BLOCK) (&s_wcnt[0][0])[i] = 0;
       const uint32_t n_cur = n;
@@ -629,13 +711,9 @@ __global__ __launch_bounds__(BLOCK) void k_pass_chunked(PassArgs a, ChunkArgs c)
         n = (uint32_t)min((uint64_t)TILE, lo + nk - start);
         pass_load<ITEMS, PACKETS>(a, start, n, wbase, lane, TILE, key);
       }
-      for (uint32_t i = tid; i < n_cur; i += BLOCK) {
-        const uint64_t x = s_keys[i];
-        const uint32_t d = (uint32_t)(x >> shift) & 255u;
-        a.out[s_gbase[d] + (i - s_lstart[d])] = x;
-      }
+      write_tile<BLOCK, ITEMS>(s_keys, s_gdel, n_cur, shift, tid, a.out);
       __syncthreads();
-      if (tid < kBins) s_gbase[tid] += s_tot[tid];
+      gbase += tot;
     }
     __syncthreads();
   }
@@ -681,6 +759,74 @@ __device__ uint64_t run_end_wave(const uint64_t *keys, uint64_t lo, uint64_t hi,
 }
 
 // ---------------------------------------------------------------------------
+// Tiles of the run scans (k_rle, k_runs), handed out by ticket one tile ahead:
+// while a workgroup resolves tile t, its fourth wave claims the next ticket and
+// finds its segment, and once t's offsets are known the next tile's keys are
+// requested, so their latency overlaps t's writes. Tickets still reach every
+// workgroup in increasing order and each finishes its current tile before it
+// starts the claimed one, so every look-back wait ends.
+// ---------------------------------------------------------------------------
+struct ScanTile {
+  uint32_t t, w, first, n;   // ticket (= tile), segment, its first tile, keys in the tile
+  uint64_t seg_lo, seg_hi, start;
+};
+
+// Claim the next ticket and its segment; called by one whole wave, lane 0
+// stores them.
+__device__ __forceinline__ void claim_tile(uint32_t *ticket, const uint64_t *tile_off, uint32_t W,
+                                           uint64_t total, uint32_t *s_t, uint32_t *s_w) {
+  const int lane = threadIdx.x & (kWave - 1);
+  uint32_t k0 = 0;
+  if (lane == 0) k0 = atomicAdd(ticket, 1u);
+  const uint32_t k = __builtin_amdgcn_readfirstlane(k0);
+  const uint32_t w = k < total ? find_owner(tile_off, W, k) : 0u;
+  if (lane == 0) {
+    *s_t = k;
+    *s_w = w;
+  }
+}
+
+__device__ __forceinline__ ScanTile scan_tile(const uint64_t *tile_off, const uint64_t *seg_off,
+                                              uint32_t t_lds, uint32_t w_lds, uint64_t total,
+                                              uint32_t tile) {
+  ScanTile g;
+  g.t = __builtin_amdgcn_readfirstlane(t_lds);
+  g.w = __builtin_amdgcn_readfirstlane(w_lds);
+  g.first = 0;
+  g.n = 0;
+  g.seg_lo = g.seg_hi = g.start = 0;
+  if (g.t < total) {
+    g.first = (uint32_t)tile_off[g.w];
+    g.seg_lo = seg_off[g.w];
+    g.seg_hi = seg_off[g.w + 1];
+    g.start = g.seg_lo + (uint64_t)(g.t - g.first) * tile;
+    g.n = (uint32_t)min((uint64_t)tile, g.seg_hi - g.start);
+  }
+  return g;
+}
+
+// Striped loads of a tile (thread i holds positions i, i+BLOCK, ...), the key
+// before it (thread 0; only inside the segment) and the key after it (wave 2,
+// which searches past the tile end; only inside the segment).
+template <int BLOCK, int ITEMS>
+__device__ __forceinline__ void scan_load(const uint64_t *keys, const ScanTile &g, uint64_t (&kr)[ITEMS],
+                                          uint64_t &kprev, uint64_t &knext) {
+  const int tid = threadIdx.x;
+  // opaque copy of the thread index: keeps the compiler from hoisting one
+  // 64-bit address per item out of the tile loop (registers it lacks)
+  uint32_t tb = tid;
+  asm volatile("" : "+v"(tb));
+  const uint64_t *base = keys + g.start;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const uint32_t i = tb + k * BLOCK;
+    kr[k] = i < g.n ? base[i] : 0;
+  }
+  if (tid == 0 && g.n && g.start > g.seg_lo) kprev = keys[g.start - 1];
+  if (tid / kWave == 2 && g.n && g.start + g.n < g.seg_hi) knext = keys[g.start + g.n];
+}
+
+// ---------------------------------------------------------------------------
 // Run-length encoding of sorted packet keys, with row heads.
 // A link head is a position whose key differs from its predecessor in the
 // segment (Table I: unique links = nonzeros of A); a row head is one whose
@@ -691,10 +837,23 @@ __device__ uint64_t run_end_wave(const uint64_t *keys, uint64_t lo, uint64_t hi,
 // end for the last run). Each row head records its packet position and link
 // index; differences of consecutive row heads give per-source packets and
 // fan-out. May run in place (ukeys == keys): a tile finishes every read beyond
-// its end before it publishes, and later tiles write only after that.
+// its end before it publishes, and later tiles write only after that; a tile
+// writes only at or below its own last position, so keys requested ahead for a
+// later tile are never overwritten first (the one position just below a tile
+// that an earlier tile may rewrite gets the same key back).
 // ---------------------------------------------------------------------------
+// Waves per SIMD that the register allocation of a run scan must allow: the
+// occupancy its LDS allows (a workgroup of 256 threads holds about KIB KiB per
+// item per thread, of 160 KiB per CU, and puts one wave on each SIMD), but no
+// more than 6, above which the keys held for the next tile would spill.
+template <int ITEMS, int KIB>
+constexpr int scan_waves() {
+  return 160 / (KIB * ITEMS) < 6 ? 160 / (KIB * ITEMS) : 6;
+}
+
 template <int ITEMS>
-__global__ __launch_bounds__(256) void k_rle(RleArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_waves<ITEMS, 4>())))
+void k_rle(RleArgs a) {
   constexpr int BLOCK = 256;
   constexpr int TILE = BLOCK * ITEMS;
   static_assert(ITEMS <= 32, "head masks are 32-bit");
@@ -705,26 +864,29 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
   __shared__ uint16_t s_rlr[TILE];    // tile-local link rank of each row head
   __shared__ uint64_t s_tmp[BLOCK / kWave];
   __shared__ uint64_t s_L0, s_R0, s_trail, s_base;
-  __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_next, s_next_w;
 
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wv = tid / kWave;
   const uint64_t total = a.tile_off[a.W];
-  for (;;) {
-    if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
-    __syncthreads();
-    const uint32_t t = s_tile;
-    if (t >= total) break;
-    const uint32_t w = find_owner(a.tile_off, a.W, t);
-    const uint32_t first = (uint32_t)a.tile_off[w];
-    const uint64_t seg_lo = a.seg_off[w], seg_hi = a.seg_off[w + 1];
-    const uint64_t start = seg_lo + (uint64_t)(t - first) * TILE;
-    const uint32_t n = (uint32_t)min((uint64_t)TILE, seg_hi - start);
+  const bool in_place = a.ukeys == a.keys;
+  if (wv == 3) claim_tile(a.ticket, a.tile_off, a.W, total, &s_next, &s_next_w);
+  __syncthreads();
+  ScanTile g = scan_tile(a.tile_off, a.seg_off, s_next, s_next_w, total, TILE);
+  uint64_t kr[ITEMS], kprev = 0, knext = 0;
+  scan_load<BLOCK, ITEMS>(a.keys, g, kr, kprev, knext);
 
-    for (uint32_t i = tid; i < n; i += BLOCK) s_k[pd(1 + i)] = a.keys[start + i];
+  while (g.t < total) {
+    const uint32_t t = g.t, w = g.w, first = g.first, n = g.n;
+    const uint64_t seg_lo = g.seg_lo, seg_hi = g.seg_hi, start = g.start;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t i = tid + k * BLOCK;
+      if (i < n) s_k[pd(1 + i)] = kr[k];
+    }
     if (tid == 0) {
       // predecessor of the tile's first key; at a segment start, a value that
       // differs from it in both halves so that position is a link and row head
-      s_k[pd(0)] = (start > seg_lo) ? a.keys[start - 1] : (a.keys[start] ^ 0xFFFFFFFF00000001ull);
+      s_k[pd(0)] = start > seg_lo ? kprev : (kr[0] ^ 0xFFFFFFFF00000001ull);
     }
     __syncthreads();
 
@@ -758,19 +920,18 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
     }
     // end of the tile's last run, searched past the tile by wave 2; in place, the
     // search must finish before this tile publishes (later tiles then write)
-    const bool in_place = a.ukeys == a.keys;
-    if (tid / kWave == 2) {
+    if (wv == 2) {
       uint64_t e = start + n;
       if (TL > 0 && e < seg_hi) {
         const uint64_t K = s_k[pd(n)];
-        if (a.keys[e] == K) e = run_end_wave(a.keys, e, seg_hi, K);
+        if (knext == K) e = run_end_wave(a.keys, e, seg_hi, K);
       }
       if ((tid & (kWave - 1)) == 0) s_trail = e;
     }
     if (in_place) __syncthreads();
     if (tid < 2) lb_store(a.lb + 2ull * t + tid, (t == 0 ? kLbInc : kLbAgg) | (tid == 0 ? TL : TR));
-    if (tid < 2 * kWave) {  // wave 0 resolves the link channel, wave 1 the row channel
-      const uint32_t ch = tid / kWave;
+    if (wv < 2) {  // wave 0 resolves the link channel, wave 1 the row channel
+      const uint32_t ch = wv;
       uint64_t excl = 0;
       if (t > 0) {
         excl = lb_walk_wave(a.lb, 2, ch, t);
@@ -781,7 +942,11 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
       }
     }
     __syncthreads();
+    if (wv == 3) claim_tile(a.ticket, a.tile_off, a.W, total, &s_next, &s_next_w);
+    __syncthreads();
     const uint64_t L0 = s_L0, R0 = s_R0, trail = s_trail;
+    g = scan_tile(a.tile_off, a.seg_off, s_next, s_next_w, total, TILE);
+    scan_load<BLOCK, ITEMS>(a.keys, g, kr, kprev, knext);  // next tile, in flight below
     // positional per-segment output: global link index at this segment's start,
     // published by the segment's first tile (an earlier ticket, so it arrives)
     if (a.win_keys && tid == 0) {
@@ -854,10 +1019,12 @@ __global__ __launch_bounds__(256) void k_rle(RleArgs a) {
 //   item's count.
 // Heads are compacted with a two-channel look-back (heads, value prefix); each
 // head stores its position and the exclusive value prefix, so consecutive
-// heads give run length (fan-out / fan-in) and run sum (packets).
+// heads give run length (fan-out / fan-in) and run sum (packets). Tiles come
+// one ahead as in k_rle.
 // ---------------------------------------------------------------------------
 template <int ITEMS, int MODE>
-__global__ __launch_bounds__(256) void k_runs(RunArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_waves<ITEMS, 5>())))
+void k_runs(RunArgs a) {
   constexpr int BLOCK = 256;
   constexpr int TILE = BLOCK * ITEMS;
   static_assert(TILE <= 65536, "tile positions are 16-bit");
@@ -867,33 +1034,46 @@ __global__ __launch_bounds__(256) void k_runs(RunArgs a) {
   __shared__ uint32_t s_hv[TILE];      // tile-local exclusive value prefix at head
   __shared__ uint64_t s_tmp[BLOCK / kWave];
   __shared__ uint64_t s_H0, s_V0;
-  __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_next, s_next_w;
 
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wv = tid / kWave;
   const uint64_t total = a.tile_off[a.W];
-  for (;;) {
-    if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
-    __syncthreads();
-    const uint32_t t = s_tile;
-    if (t >= total) break;
-    const uint32_t w = find_owner(a.tile_off, a.W, t);
-    const uint32_t first = (uint32_t)a.tile_off[w];
-    const uint64_t seg_lo = a.seg_off[w], seg_hi = a.seg_off[w + 1];
-    const uint64_t start = seg_lo + (uint64_t)(t - first) * TILE;
-    const uint32_t n = (uint32_t)min((uint64_t)TILE, seg_hi - start);
-
-    for (uint32_t i = tid; i < n; i += BLOCK) {
-      const uint64_t k = a.keys[start + i];
-      s_g[pd(1 + i)] = k >> 32;
-      if (MODE == 0) {
-        const uint64_t c = a.counts[start + i];
-        s_v[pd(i)] = (uint32_t)c;
-        if (a.items) a.items[start + i] = (k << 32) | c;
-      } else {
-        s_v[pd(i)] = (uint32_t)k;
+  if (wv == 3) claim_tile(a.ticket, a.tile_off, a.W, total, &s_next, &s_next_w);
+  __syncthreads();
+  ScanTile g = scan_tile(a.tile_off, a.seg_off, s_next, s_next_w, total, TILE);
+  uint64_t kr[ITEMS], cr[ITEMS], kprev = 0, knext = 0;
+  auto load = [&]() {
+    scan_load<BLOCK, ITEMS>(a.keys, g, kr, kprev, knext);
+    if (MODE == 0) {
+      uint32_t tb = tid;
+      asm volatile("" : "+v"(tb));
+      const uint64_t *base = a.counts + g.start;
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t i = tb + k * BLOCK;
+        cr[k] = i < g.n ? base[i] : 0;
       }
     }
-    if (tid == 0) s_g[pd(0)] = (start > seg_lo) ? (a.keys[start - 1] >> 32) : ~0ull;
+  };
+  load();
+
+  while (g.t < total) {
+    const uint32_t t = g.t, w = g.w, first = g.first, n = g.n;
+    const uint64_t seg_lo = g.seg_lo, start = g.start;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t i = tid + k * BLOCK;
+      if (i < n) {
+        s_g[pd(1 + i)] = kr[k] >> 32;
+        if (MODE == 0) {
+          s_v[pd(i)] = (uint32_t)cr[k];
+          if (a.items) a.items[start + i] = (kr[k] << 32) | cr[k];
+        } else {
+          s_v[pd(i)] = (uint32_t)kr[k];
+        }
+      }
+    }
+    if (tid == 0) s_g[pd(0)] = start > seg_lo ? (kprev >> 32) : ~0ull;
     __syncthreads();
 
     uint32_t hmask = 0, vsum = 0;
@@ -924,8 +1104,8 @@ __global__ __launch_bounds__(256) void k_runs(RunArgs a) {
       }
     }
     if (tid < 2) lb_store(a.lb + 2ull * t + tid, (t == 0 ? kLbInc : kLbAgg) | (tid == 0 ? TH : TV));
-    if (tid < 2 * kWave) {  // wave 0: head channel, wave 1: value channel
-      const uint32_t ch = tid / kWave;
+    if (wv < 2) {  // wave 0: head channel, wave 1: value channel
+      const uint32_t ch = wv;
       uint64_t excl = 0;
       if (t > 0) {
         excl = lb_walk_wave(a.lb, 2, ch, t);
@@ -936,7 +1116,11 @@ __global__ __launch_bounds__(256) void k_runs(RunArgs a) {
       }
     }
     __syncthreads();
+    if (wv == 3) claim_tile(a.ticket, a.tile_off, a.W, total, &s_next, &s_next_w);
+    __syncthreads();
     const uint64_t H0 = s_H0, V0 = s_V0;
+    g = scan_tile(a.tile_off, a.seg_off, s_next, s_next_w, total, TILE);
+    load();  // next tile, in flight below
     if (tid == 0) {
       if (t == first) {
         a.head_off[w] = H0;
@@ -973,7 +1157,7 @@ __global__ __launch_bounds__(256) void k_max_counts(const uint64_t *counts, cons
   const uint64_t per = (total + gridDim.x - 1) / gridDim.x;
   const uint64_t p0 = (uint64_t)blockIdx.x * per, p1 = min(total, p0 + per);
   if (p0 >= p1) return;  // the whole workgroup leaves together
-  uint32_t w = off ? find_owner(off, W, p0) : 0;
+  uint32_t w = off ? find_owner_wave(off, W, p0) : 0;
   for (; w < W; ++w) {
     const uint64_t lo = off ? off[w] : 0;
     if (lo >= p1) break;
@@ -1007,7 +1191,7 @@ __global__ __launch_bounds__(256) void k_segmax(const uint64_t *a, const uint64_
   const uint64_t lo = blockIdx.x * chunk, hi = min(lo + chunk, total);
   if (lo >= hi) return;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  const uint32_t w0 = find_owner(head_off, W, lo), w1 = find_owner(head_off, W, hi - 1);
+  const uint32_t w0 = find_owner_wave(head_off, W, lo), w1 = find_owner_wave(head_off, W, hi - 1);
   for (uint32_t w = w0; w <= w1; ++w) {
     const uint64_t plo = max(lo, head_off[w]), phi = min(hi, head_off[w + 1]);
     if (plo >= phi) continue;  // uniform: every thread sees the same bounds

@@ -120,7 +120,7 @@ hipError_t launch_rle(const ScanShape &sh, const RleArgs &a, uint64_t max_tiles,
 
 // --- run reduction over a sorted array with explicit values -----------------------
 // mode 0: rows of a matrix (group = key>>32, value = counts[p]); also emits
-//         column items and their digit histograms.
+//         column items.
 // mode 1: columns of sorted items (group = item>>32, value = item & 0xffffffff).
 struct RunArgs {
   const uint64_t *keys;
