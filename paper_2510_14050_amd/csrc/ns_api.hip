@@ -33,6 +33,8 @@ constexpr uint64_t kForkMaxPackets = NS_FORK_MAX_PACKETS;
 constexpr uint64_t kMaxPackets32 = 0xFFFFFFFFull;  // packets per window / matrix < 2^32
 constexpr int kMinSortTile = 256 * 8;
 constexpr int kMinScanTile = 256 * 4;
+constexpr int kChunkBlock = 512, kChunkItems = 16;  // launch shape of the chunked passes
+constexpr uint64_t kChunkTile = (uint64_t)kChunkBlock * kChunkItems;
 
 uint64_t up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
@@ -43,7 +45,8 @@ struct Layout {
   uint64_t link_off, row_off, col_off, seg_base;
   uint64_t hist, base, chist, cbase;
   uint64_t lb0, lb1, lbs;
-  uint64_t ccount, cprefix;
+  uint64_t ccount, cprefix, cbsum;
+  uint64_t chunk_rows;
   uint64_t KA, KB, HA, HB;
   uint64_t total;
   uint64_t sort_tiles, scan_tiles;
@@ -75,8 +78,10 @@ Layout plan(uint64_t N, uint32_t W) {
   L.lb0 = take(L.sort_tiles * kBins * 8);
   L.lb1 = take(L.sort_tiles * kBins * 8);
   L.lbs = take(L.scan_tiles * 2 * 8);
-  L.ccount = take((uint64_t)kChunks * kBins * 4);
-  L.cprefix = take((uint64_t)(kChunks + 1) * kBins * 8);  // + digit totals
+  L.chunk_rows = chunk_rows(N, kChunkTile);
+  L.ccount = take(L.chunk_rows * kBins * 4);
+  L.cprefix = take((L.chunk_rows + 1) * kBins * 8);  // + digit totals
+  L.cbsum = take((uint64_t)kChunkBlocks * kBins * 8);
   L.KA = take((N + 1) * 8);
   L.KB = take((N + 1) * 8);
   L.HA = take((N + 2) * 8);
@@ -94,6 +99,18 @@ struct Ws {
   T *at(uint64_t off) const { return reinterpret_cast<T *>(base + off); }
   uint32_t *ticket() { return at<uint32_t>(L.tickets) + (next_ticket++ % kMaxTickets); }
 };
+
+// Chunk tables of a chunked pass over the segment [seg_off[0], seg_off[1]).
+ChunkArgs chunk_args(const Ws &ws, const uint64_t *seg_off) {
+  ChunkArgs c{};
+  c.seg_off = seg_off;
+  c.max_chunks = (uint32_t)ws.L.chunk_rows;
+  c.count = ws.at<uint32_t>(ws.L.ccount);
+  c.prefix = ws.at<uint64_t>(ws.L.cprefix);
+  c.total = ws.at<uint64_t>(ws.L.cprefix) + ws.L.chunk_rows * kBins;
+  c.bsum = ws.at<uint64_t>(ws.L.cbsum);
+  return c;
+}
 
 #define HIP_TRY(expr)                           \
   do {                                          \
@@ -151,7 +168,7 @@ struct Shapes {
   uint64_t chunked_min = kChunkedMin;
   // chunked passes: the largest tile measured fastest (fewest tiles per chunk
   // boundary, most keys per digit run)
-  SortShape chunk = {512, 16};
+  SortShape chunk = {kChunkBlock, kChunkItems};
 };
 
 int resolve_tuning(const ns_tuning_t *t, Shapes *sh) {
@@ -220,8 +237,7 @@ int enqueue_columns(Ws &ws, const Shapes &sh, uint64_t *items, uint64_t *tmp,
       a.shift = 32 + 8 * q;
       a.ticket = ws.ticket();
       if (chunked) {
-        ChunkArgs c{link_off, 0, ws.at<uint32_t>(L.ccount), ws.at<uint64_t>(L.cprefix),
-                    ws.at<uint64_t>(L.cprefix) + (uint64_t)kChunks * kBins};
+        const ChunkArgs c = chunk_args(ws, link_off);
         const hipError_t e = launch_pass_chunked(sh.chunk, a, c, max_items, K_CHUNK_COUNT, s);
         if (e != hipSuccess) return e;
         continue;
@@ -321,8 +337,7 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
     a.shift = 8 * p;
     a.ticket = ws.ticket();
     if (chunked) {
-      ChunkArgs c{seg_off, 0, ws.at<uint32_t>(L.ccount), ws.at<uint64_t>(L.cprefix),
-                  ws.at<uint64_t>(L.cprefix) + (uint64_t)kChunks * kBins};
+      const ChunkArgs c = chunk_args(ws, seg_off);
       return launch_pass_chunked(sh.chunk, a, c, N, K_CHUNK_COUNT, s);
     }
     a.seg_off = seg_off;

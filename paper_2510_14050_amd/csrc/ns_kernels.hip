@@ -19,9 +19,6 @@
 #define NS_HIST_BLOCK 512  // threads of a histogram workgroup
 #endif
 constexpr int kHistBlock = NS_HIST_BLOCK;
-#ifndef NS_CHUNKS_PER_CU
-#define NS_CHUNKS_PER_CU 2  // chunks of a large single-segment pass per CU
-#endif
 #ifndef NS_LB_DEPTH
 #define NS_LB_DEPTH 4  // look-back words in flight per thread and round trip
 #endif
@@ -569,14 +566,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 //
 // With a single segment, every tile's look-back walks a long chain of tiles
 // still in flight, and each step is a round trip to memory. Here the segment
-// is cut into at most kChunks chunks of whole tiles instead: k_chunk_hist
-// counts each chunk's digits, k_chunk_scan sums them over earlier chunks per
-// digit, and k_pass_chunked sorts each chunk's tiles in order, starting from
-// those positions (plus the start of the digit's bucket) and carrying its own
-// running offsets from tile to tile. The keys are read twice, but nothing ever waits.
-// The tile count, the chunk length and the chunk count follow from the
-// segment length on the device, so a launch sized for n keys serves any
-// length up to n.
+// is cut into short chunks of whole tiles instead (kChunkTiles each, within the
+// rows of the chunk tables): k_chunk_hist counts each chunk's digits, the
+// chunk scan sums them over earlier chunks per digit, and k_pass_chunked sorts
+// each chunk's tiles in order, starting from those positions (plus the start
+// of the digit's bucket) and carrying its own running offsets from tile to
+// tile. The keys are read twice, but nothing ever waits. Chunks are taken by
+// ticket, so the ones in flight are neighbours and their writes to each digit's
+// bucket stay close together. The tile count, the chunk length and the chunk
+// count follow from the segment length on the device, so a launch sized for n
+// keys serves any length up to n.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void chunk_geometry(const ChunkArgs &c, uint32_t tile, uint64_t *lo,
                                                uint64_t *n, uint64_t *tiles, uint64_t *per) {
@@ -623,32 +622,52 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_hist(PassArgs a, ChunkArgs c, u
   }
 }
 
-// One workgroup per digit d: prefix[ch][d] = keys with digit d in chunks
-// before ch; total[d] = keys with digit d. Each thread sums a run of
-// consecutive chunks, so one round of loads covers the whole column.
-__global__ __launch_bounds__(256) void k_chunk_scan(ChunkArgs c) {
+// The chunk scan: prefix[ch][d] = keys with digit d in chunks before ch, and
+// total[d] = keys with digit d, in three coalesced steps over the row-major
+// count table (a row is the 256 counts of one chunk): each workgroup sums the
+// rows of one block of consecutive chunks, the block sums are scanned per
+// digit, and each block then writes its chunks' prefixes from its own start.
+// Thread d of every workgroup owns digit d, so each row is one 1 KiB read.
+__global__ __launch_bounds__(256) void k_chunk_sums(ChunkArgs c, uint32_t rows) {
+  const uint32_t r0 = blockIdx.x * rows, r1 = min(c.chunks, r0 + rows), d = threadIdx.x;
+  uint64_t s = 0;
+  for (uint32_t r = r0; r < r1; ++r) s += c.count[(uint64_t)r * kBins + d];
+  c.bsum[(uint64_t)blockIdx.x * kBins + d] = s;
+}
+
+// One workgroup per digit; thread i scans blocks [i*per, (i+1)*per).
+__global__ __launch_bounds__(256) void k_chunk_bscan(ChunkArgs c, uint32_t blocks) {
   __shared__ uint64_t s_tmp[4];
+  constexpr int kMaxPer = kChunkBlocks / 256;
   const uint32_t d = blockIdx.x;
-  const uint32_t per = (c.chunks + 255) / 256;  // <= kChunks / 256
-  constexpr int kMaxPer = kChunks / 256;
-  const uint32_t r0 = threadIdx.x * per;
-  uint32_t v[kMaxPer];
+  const uint32_t per = (blocks + 255) / 256;
+  const uint32_t b0 = threadIdx.x * per;
+  uint64_t v[kMaxPer];
   uint64_t sum = 0;
 #pragma unroll
   for (int q = 0; q < kMaxPer; ++q) {
-    const uint32_t r = r0 + q;
-    v[q] = (q < (int)per && r < c.chunks) ? c.count[(uint64_t)r * kBins + d] : 0;
+    const uint32_t b = b0 + q;
+    v[q] = (q < (int)per && b < blocks) ? c.bsum[(uint64_t)b * kBins + d] : 0;
     sum += v[q];
   }
   uint64_t tot;
   uint64_t run = block_excl_scan<256>(sum, s_tmp, &tot);
 #pragma unroll
   for (int q = 0; q < kMaxPer; ++q) {
-    const uint32_t r = r0 + q;
-    if (q < (int)per && r < c.chunks) c.prefix[(uint64_t)r * kBins + d] = run;
+    const uint32_t b = b0 + q;
+    if (q < (int)per && b < blocks) c.bsum[(uint64_t)b * kBins + d] = run;
     run += v[q];
   }
   if (threadIdx.x == 0) c.total[d] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_chunk_prefix(ChunkArgs c, uint32_t rows) {
+  const uint32_t r0 = blockIdx.x * rows, r1 = min(c.chunks, r0 + rows), d = threadIdx.x;
+  uint64_t run = c.bsum[(uint64_t)blockIdx.x * kBins + d];
+  for (uint32_t r = r0; r < r1; ++r) {
+    c.prefix[(uint64_t)r * kBins + d] = run;
+    run += c.count[(uint64_t)r * kBins + d];
+  }
 }
 
 template <int BLOCK, int ITEMS, bool PACKETS>
@@ -1573,24 +1592,27 @@ hipError_t launch_pass(const SortShape &sh, const PassArgs &a, uint64_t max_tile
 template <int B, int I, bool P>
 static hipError_t pass_chunked_impl(const PassArgs &a, ChunkArgs c, uint64_t max_keys,
                                     int count_kind, hipStream_t s) {
-  static uint64_t cap[64];
+  static uint64_t cap[64], hcap[64];
   const int d = device_id();
   if (!cap[d]) cap[d] = resident(k_pass_chunked<B, I, P>, B);
-  // one chunk per resident workgroup (at most NS_CHUNKS_PER_CU per CU), each
-  // of at least two tiles: every chunk starts at once and none waits for a
-  // free slot
-  uint64_t ch = (uint64_t)NS_CHUNKS_PER_CU * cu_count();
-  if (ch > cap[d]) ch = cap[d];
-  if (ch > kChunks) ch = kChunks;
-  const uint64_t tiles = (max_keys + B * I - 1) / (B * I);
-  if (ch > tiles / 2) ch = tiles / 2;
-  c.chunks = (uint32_t)(ch ? ch : 1);
+  if (!hcap[d]) hcap[d] = resident(k_chunk_hist<256, P>, 256);
+  // short chunks of kChunkTiles tiles, taken in order by the resident
+  // workgroups: the chunks in flight at any time are neighbours, so each
+  // digit's writes land in one narrow band of its bucket
+  uint64_t ch = chunk_rows(max_keys, (uint64_t)B * I);
+  if (ch > c.max_chunks) ch = c.max_chunks;
+  c.chunks = (uint32_t)ch;
+  const uint32_t blocks = (uint32_t)(ch < kChunkBlocks ? ch : kChunkBlocks);
+  const uint32_t rows = (uint32_t)((ch + blocks - 1) / blocks);
+  const uint32_t nb = (uint32_t)((ch + rows - 1) / rows);
   const int kind = tl_timing_kind;
   if (kind >= 0) tl_timing_kind = count_kind;
-  NS_LAUNCH((k_chunk_hist<256, P>), dim3(c.chunks), dim3(256), s, a, c, (uint32_t)(B * I));
-  NS_LAUNCH(k_chunk_scan, dim3(kBins), dim3(256), s, c);
+  NS_LAUNCH((k_chunk_hist<256, P>), dim3(clamp_grid(ch, hcap[d])), dim3(256), s, a, c, (uint32_t)(B * I));
+  NS_LAUNCH(k_chunk_sums, dim3(nb), dim3(256), s, c, rows);
+  NS_LAUNCH(k_chunk_bscan, dim3(kBins), dim3(256), s, c, nb);
+  NS_LAUNCH(k_chunk_prefix, dim3(nb), dim3(256), s, c, rows);
   tl_timing_kind = kind;
-  NS_LAUNCH((k_pass_chunked<B, I, P>), dim3(c.chunks), dim3(B), s, a, c);
+  NS_LAUNCH((k_pass_chunked<B, I, P>), dim3(clamp_grid(ch, cap[d])), dim3(B), s, a, c);
   return hipGetLastError();
 }
 

@@ -81,12 +81,23 @@ struct PassArgs {
 hipError_t launch_pass(const SortShape &sh, const PassArgs &a, uint64_t max_tiles, hipStream_t s);
 
 // --- radix pass over one large segment: reduce, scan, scatter (no look-back) ---
-constexpr uint32_t kChunks = 1024;  // most chunks per pass (rows of count / prefix)
+#ifndef NS_CHUNK_TILES
+#define NS_CHUNK_TILES 4
+#endif
+constexpr uint32_t kChunkTiles = NS_CHUNK_TILES;  // tiles per chunk
+constexpr uint32_t kChunkBlocks = 1024;            // most row blocks of the chunk scan
+// rows of the chunk tables for a segment of n keys in tiles of `tile` keys
+inline uint64_t chunk_rows(uint64_t n, uint64_t tile) {
+  const uint64_t r = (n + tile * kChunkTiles - 1) / (tile * kChunkTiles);
+  return r ? r : 1;
+}
 struct ChunkArgs {
   const uint64_t *seg_off;  // [2]: the segment is [seg_off[0], seg_off[1])
-  uint32_t chunks;          // set by the launcher (<= kChunks)
-  uint32_t *count;          // [kChunks][256] digit counts per chunk
-  uint64_t *prefix;         // [kChunks][256] keys of the digit in earlier chunks
+  uint32_t chunks;          // set by the launcher (<= max_chunks)
+  uint32_t max_chunks;      // rows of count and prefix
+  uint32_t *count;          // [max_chunks][256] digit counts per chunk
+  uint64_t *prefix;         // [max_chunks][256] keys of the digit in earlier chunks
+  uint64_t *bsum;           // [kChunkBlocks][256] per row block: sum, then exclusive prefix
   uint64_t *total;          // [256] keys per digit
 };
 // Sorts at most max_keys keys. a.seg_off / tile_off / W / base / lb are unused;
