@@ -143,9 +143,13 @@ __global__ __launch_bounds__(BLOCK) void k_hist(const uint32_t *__restrict__ src
   const uint32_t cp = threadIdx.x & (C - 1);
   for (int i = threadIdx.x; i < NC * C; i += BLOCK) s_h[i] = 0;
   __syncthreads();
+  // workgroups start their flush at different bins, so the ones that finish
+  // together do not queue on the same counters
+  const uint32_t rot = (blockIdx.x * BLOCK) % NC;
   auto flush = [&](uint32_t w) {
     uint32_t *g = hist + (uint64_t)w * NC;
-    for (int i = threadIdx.x; i < NC; i += BLOCK) {
+    for (int i0 = threadIdx.x; i0 < NC; i0 += BLOCK) {
+      const int i = (i0 + rot) % NC;
       uint32_t c = 0;
 #pragma unroll
       for (int k = 0; k < C; ++k) {
@@ -1189,7 +1193,7 @@ __global__ __launch_bounds__(256) void k_max_counts(const uint64_t *counts, cons
     __syncthreads();
     if (threadIdx.x == 0) {
       const uint64_t v = max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3]));
-      if (v) atomicMax(reinterpret_cast<unsigned long long *>(out + w), (unsigned long long)v);
+      if (v > lb_load(out + w)) atomicMax(reinterpret_cast<unsigned long long *>(out + w), (unsigned long long)v);
     }
     __syncthreads();
   }
@@ -1215,10 +1219,24 @@ __global__ __launch_bounds__(256) void k_segmax(const uint64_t *a, const uint64_
     const uint64_t plo = max(lo, head_off[w]), phi = min(hi, head_off[w + 1]);
     if (plo >= phi) continue;  // uniform: every thread sees the same bounds
     uint64_t ma = 0, mb = 0;
-    for (uint64_t r = plo + tid; r < phi; r += 256) {
-      const uint64_t da = a[r + 1] - a[r], db = b[r + 1] - b[r];
-      ma = ma > da ? ma : da;
-      mb = mb > db ? mb : db;
+    constexpr int R = 4;  // rounds of loads issued together
+    for (uint64_t r0 = plo + tid; r0 < phi; r0 += R * 256) {
+      uint64_t a0[R], a1[R], b0[R], b1[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const uint64_t r = r0 + q * 256;
+        const bool in = r < phi;
+        a0[q] = in ? a[r] : 0;
+        a1[q] = in ? a[r + 1] : 0;
+        b0[q] = in ? b[r] : 0;
+        b1[q] = in ? b[r + 1] : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const uint64_t da = a1[q] - a0[q], db = b1[q] - b0[q];
+        ma = ma > da ? ma : da;
+        mb = mb > db ? mb : db;
+      }
     }
     ma = wave_max(ma);
     mb = wave_max(mb);
@@ -1232,8 +1250,13 @@ __global__ __launch_bounds__(256) void k_segmax(const uint64_t *a, const uint64_
         ma = ma > s_ma[q] ? ma : s_ma[q];
         mb = mb > s_mb[q] ? mb : s_mb[q];
       }
-      atomicMax((unsigned long long *)&stats[(uint64_t)w * 8 + fa], (unsigned long long)ma);
-      atomicMax((unsigned long long *)&stats[(uint64_t)w * 8 + fb], (unsigned long long)mb);
+      // With many workgroups per window their atomics would queue on the same
+      // two words; maxima only grow, so a value not above the one already there
+      // (even a stale read of it) needs none, and few workgroups issue one.
+      uint64_t *pa = &stats[(uint64_t)w * 8 + fa], *pb = &stats[(uint64_t)w * 8 + fb];
+      const bool crowded = gridDim.x > 8ull * W;
+      if (!crowded || ma > lb_load(pa)) atomicMax((unsigned long long *)pa, (unsigned long long)ma);
+      if (!crowded || mb > lb_load(pb)) atomicMax((unsigned long long *)pb, (unsigned long long)mb);
     }
     __syncthreads();
   }
