@@ -106,6 +106,38 @@ __device__ __forceinline__ uint32_t find_owner(const uint64_t *off, uint32_t W, 
   return lo;
 }
 
+// The same owner, searched from the proportional guess t*W/total (total =
+// off[W] > t): galloping out from the guess brackets the answer, then a
+// binary search narrows the bracket. Segments of about equal length take two
+// loads; a guess d segments off takes about 2 log2 d.
+__device__ __forceinline__ uint32_t find_owner_near(const uint64_t *off, uint32_t W, uint64_t total,
+                                                    uint64_t t) {
+  uint64_t lo, hi;  // off[lo] <= t < off[hi] (hi == W stands for +infinity)
+  uint64_t g = t * W / total;
+  if (g >= W) g = W - 1;
+  if (off[g] <= t) {
+    lo = g;
+    for (uint64_t s = 1;; s <<= 1) {
+      const uint64_t c = lo + s;
+      if (c >= W) { hi = W; break; }
+      if (off[c] > t) { hi = c; break; }
+      lo = c;
+    }
+  } else {
+    hi = g;  // off[0] == 0 <= t, so this ends
+    for (uint64_t s = 1;; s <<= 1) {
+      const uint64_t c = hi > s ? hi - s : 0;
+      if (off[c] <= t) { lo = c; break; }
+      hi = c;
+    }
+  }
+  while (hi - lo > 1) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= t) lo = mid; else hi = mid;
+  }
+  return (uint32_t)lo;
+}
+
 // The same owner, searched by a whole wave (all 64 lanes active, t uniform)
 // where t is not known to be uniform: each round probes 64 evenly spaced
 // entries of the remaining range, so W segments take ceil(log64 W) dependent

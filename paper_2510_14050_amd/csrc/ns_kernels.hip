@@ -802,7 +802,7 @@ __device__ __forceinline__ void claim_tile(uint32_t *ticket, const uint64_t *til
   uint32_t k0 = 0;
   if (lane == 0) k0 = atomicAdd(ticket, 1u);
   const uint32_t k = __builtin_amdgcn_readfirstlane(k0);
-  const uint32_t w = k < total ? find_owner(tile_off, W, k) : 0u;
+  const uint32_t w = k < total ? find_owner_near(tile_off, W, total, k) : 0u;
   if (lane == 0) {
     *s_t = k;
     *s_w = w;
