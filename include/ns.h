@@ -133,6 +133,32 @@ int ns_build_matrix(const uint32_t *src, const uint32_t *dst, uint64_t n, ns_mat
 int ns_accumulate(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
                   ns_matrix_t *acc_out, void *ws, uint64_t ws_bytes, void *stream);
 
+/* Out-of-core build (Sec. III-C "Concurrent Batching", Fig. 3: input data
+ * held on the host is cut into b_n batches that are moved to the GPU one
+ * after the other during the computation). The n packets in HOST memory
+ * (src, dst: n uint32 each; page-locked memory lets the copies overlap the
+ * kernels) are taken in b_n = ceil(n / batch) sub-partitions of `batch`
+ * packets: sub-partition k+1 is copied to the device on `copy_stream` while
+ * sub-partition k is built into its matrix on `stream` (as ns_build_matrix),
+ * which is then union-added into the running aggregate (as ns_accumulate).
+ * On return (asynchronously) `out` holds the matrix of all n packets, exactly
+ * as ns_build_matrix would build it: the result does not depend on `batch`.
+ *   batch        packets per sub-partition, 1 .. 2^32-1
+ *   out          device matrix; out->capacity bounds the links of the
+ *                aggregate (it must be >= min(n, batch)); out->packets = n.
+ *                If the links exceed it, the first out->capacity links are
+ *                kept, *out->nnz = out->capacity, and ns_device_status
+ *                reports NS_ERR_CAPACITY.
+ *   ws, ws_bytes device workspace of ns_stream_workspace_size(batch,
+ *                out->capacity) bytes (256-byte aligned)
+ *   copy_stream  stream of the host-to-device copies (NULL: `stream`); the
+ *                host memory must stay valid until `stream` has completed
+ * Not capturable into a graph (it orders two streams with events). */
+int ns_stream_workspace_size(uint64_t batch, uint64_t capacity, uint64_t *bytes);
+int ns_build_matrix_streamed(const uint32_t *src, const uint32_t *dst, uint64_t n, uint64_t batch,
+                             ns_matrix_t *out, void *ws, uint64_t ws_bytes, void *stream,
+                             void *copy_stream);
+
 /* The eight quantities of a matrix (Table I with the row/column-sum maxima)
  * into *out (device). m->packets must be below 2^32. */
 int ns_stats(const ns_matrix_t *m, ns_stats_t *out, void *ws, uint64_t ws_bytes, void *stream);

@@ -112,6 +112,32 @@ ChunkArgs chunk_args(const Ws &ws, const uint64_t *seg_off) {
   return c;
 }
 
+// Workspace of the streamed build: the build workspace of one sub-partition,
+// two staging buffers of its packets, the sub-partition's own matrix, a second
+// aggregate of `capacity` entries (the union-add alternates between it and
+// the output) and the merge's look-back words.
+struct StreamLayout {
+  uint64_t inner, stage, bkeys, bcounts, bnnz, akeys, acounts, annz, mlb, merge_tiles, total;
+};
+
+StreamLayout stream_plan(uint64_t batch, uint64_t capacity) {
+  StreamLayout L{};
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) { const uint64_t at = o; o += up(bytes); return at; };
+  L.inner = take(plan(batch, 1).total);
+  L.stage = take(4 * batch * 4);  // src and dst of two sub-partitions
+  L.bkeys = take(batch * 8);
+  L.bcounts = take(batch * 8);
+  L.bnnz = take(8);
+  L.akeys = take(capacity * 8);
+  L.acounts = take(capacity * 8);
+  L.annz = take(8);
+  L.merge_tiles = (capacity + batch) / kMergeTile + 2;
+  L.mlb = take(L.merge_tiles * 8);
+  L.total = o;
+  return L;
+}
+
 #define HIP_TRY(expr)                           \
   do {                                          \
     if ((expr) != hipSuccess) return NS_ERR_HIP; \
@@ -748,11 +774,126 @@ int ns_accumulate(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
   a.kc = acc_out->keys;
   a.cc = acc_out->counts;
   a.nc = acc_out->nnz;
+  a.nc_max = acc_out->capacity;
   a.sign = sign;
   a.lb = lbs;
   a.ticket = w.ticket();
   HIP_TRY(timed(K_MERGE, s, [&] { return launch_merge(a, tiles, s); }));
   acc_out->packets = sign > 0 ? acc_in->packets + win->packets : acc_in->packets - win->packets;
+  return NS_OK;
+}
+
+int ns_stream_workspace_size(uint64_t batch, uint64_t capacity, uint64_t *bytes) {
+  if (!bytes || batch == 0) return NS_ERR_INVALID_ARG;
+  *bytes = stream_plan(batch, capacity).total;
+  return NS_OK;
+}
+
+int ns_build_matrix_streamed(const uint32_t *src, const uint32_t *dst, uint64_t n, uint64_t batch,
+                             ns_matrix_t *out, void *ws, uint64_t ws_bytes, void *stream,
+                             void *copy_stream) {
+  if (!out || !out->keys || !out->counts || !out->nnz) return NS_ERR_INVALID_ARG;
+  if (n > 0 && (!src || !dst)) return NS_ERR_INVALID_ARG;
+  if (batch == 0) return NS_ERR_INVALID_ARG;
+  if (batch > kMaxPackets32) return NS_ERR_UNSUPPORTED;
+  const uint64_t first = n < batch ? n : batch;
+  if (out->capacity < first) return NS_ERR_CAPACITY;
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % kAlign) return NS_ERR_WORKSPACE;
+  const StreamLayout SL = stream_plan(batch, out->capacity);
+  if (ws_bytes < SL.total) return NS_ERR_WORKSPACE;
+  uint8_t *base = static_cast<uint8_t *>(ws);
+  Ws w;
+  int rc = check_ws(base + SL.inner, ws_bytes - SL.inner, batch, 1, &w);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipStream_t cs = copy_stream ? static_cast<hipStream_t>(copy_stream) : s;
+  const uint64_t C = out->capacity;
+  const uint64_t nb = (n + batch - 1) / batch;  // b_n sub-partitions
+  if (nb == 0) {
+    HIP_TRY(launch_fill64(out->nnz, 1, 0, s));
+    out->packets = 0;
+    return NS_OK;
+  }
+  auto at64 = [&](uint64_t off) { return reinterpret_cast<uint64_t *>(base + off); };
+  uint32_t *stage = reinterpret_cast<uint32_t *>(base + SL.stage);
+  uint32_t *st_src[2] = {stage, stage + 2 * batch};
+  uint32_t *st_dst[2] = {stage + batch, stage + 3 * batch};
+  ns_matrix_t bm{at64(SL.bkeys), at64(SL.bcounts), at64(SL.bnnz), batch, 0};
+  ns_matrix_t am{at64(SL.akeys), at64(SL.acounts), at64(SL.annz), C, 0};
+  // the aggregate after sub-partition k lives in `out` when nb-1-k is even, so
+  // the last one lands there
+  auto agg = [&](uint64_t k) -> ns_matrix_t * { return ((nb - 1 - k) & 1) == 0 ? out : &am; };
+  Shapes sh;
+  resolve_tuning(nullptr, &sh);
+  hipEvent_t copied[2] = {nullptr, nullptr}, freed[2] = {nullptr, nullptr};
+  int status = NS_OK;
+  for (int b = 0; b < 2 && status == NS_OK; ++b) {
+    if (hipEventCreateWithFlags(&copied[b], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&freed[b], hipEventDisableTiming) != hipSuccess)
+      status = NS_ERR_HIP;
+  }
+  // sub-partition k goes to staging buffer k&1 once the build of k-2 has read it
+  auto copy_in = [&](uint64_t k) -> int {
+    const int b = (int)(k & 1);
+    const uint64_t off = k * batch, len = n - off < batch ? n - off : batch;
+    if (k >= 2) HIP_TRY(hipStreamWaitEvent(cs, freed[b], 0));
+    HIP_TRY(hipMemcpyAsync(st_src[b], src + off, len * 4, hipMemcpyHostToDevice, cs));
+    HIP_TRY(hipMemcpyAsync(st_dst[b], dst + off, len * 4, hipMemcpyHostToDevice, cs));
+    HIP_TRY(hipEventRecord(copied[b], cs));
+    return NS_OK;
+  };
+  if (status == NS_OK) status = copy_in(0);
+  for (uint64_t k = 0; k < nb && status == NS_OK; ++k) {
+    // the next sub-partition crosses the bus while this one is built
+    if (k + 1 < nb && (status = copy_in(k + 1)) != NS_OK) break;
+    const int b = (int)(k & 1);
+    const uint64_t len = n - k * batch < batch ? n - k * batch : batch;
+    if (hipStreamWaitEvent(s, copied[b], 0) != hipSuccess) { status = NS_ERR_HIP; break; }
+    ns_matrix_t *dest = k == 0 ? agg(0) : &bm;
+    if (launch_fill32(w.at<uint32_t>(w.L.tickets), kMaxTickets, 0, s) != hipSuccess) { status = NS_ERR_HIP; break; }
+    uint64_t *seg = w.at<uint64_t>(w.L.seg);
+    if (launch_seg1(seg, nullptr, len, s) != hipSuccess) { status = NS_ERR_HIP; break; }
+    PacketOut o{};
+    o.ukeys = dest->keys;
+    o.counts = dest->counts;
+    o.nnz = dest->nnz;
+    o.sort_a = w.at<uint64_t>(w.L.KA);
+    o.sort_b = w.at<uint64_t>(w.L.KB);
+    if ((status = enqueue_packets(w, sh, st_src[b], st_dst[b], seg, 1, len, o, s)) != NS_OK) break;
+    if (hipEventRecord(freed[b], s) != hipSuccess) { status = NS_ERR_HIP; break; }
+    if (k == 0) continue;
+    // union-add into the other aggregate buffer (Fig. 2: load and aggregate)
+    const ns_matrix_t *prev = agg(k - 1);
+    ns_matrix_t *next = agg(k);
+    uint64_t *lbs = at64(SL.mlb);
+    const uint64_t na_max = k * batch < C ? k * batch : C;
+    if (launch_fill64(lbs, SL.merge_tiles, 0, s) != hipSuccess) { status = NS_ERR_HIP; break; }
+    MergeArgs a{};
+    a.ka = prev->keys;
+    a.ca = prev->counts;
+    a.na = prev->nnz;
+    a.kb = bm.keys;
+    a.cb = bm.counts;
+    a.nb = bm.nnz;
+    a.na_max = na_max;
+    a.nb_max = len;
+    a.kc = next->keys;
+    a.cc = next->counts;
+    a.nc = next->nnz;
+    a.nc_max = C;
+    a.sign = 1;
+    a.lb = lbs;
+    a.ticket = w.ticket();
+    if (launch_merge(a, (na_max + len) / kMergeTile + 2, s) != hipSuccess) { status = NS_ERR_HIP; break; }
+  }
+  // destruction of a recorded event waits for nothing; it is released once
+  // its work completes
+  for (int b = 0; b < 2; ++b) {
+    if (copied[b]) hipEventDestroy(copied[b]);
+    if (freed[b]) hipEventDestroy(freed[b]);
+  }
+  if (status != NS_OK) return status;
+  out->packets = n;
   return NS_OK;
 }
 

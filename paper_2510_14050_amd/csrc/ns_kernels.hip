@@ -1435,7 +1435,13 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
       }
       if (tid == 0) {
         s_L0 = excl;
-        if (t == tiles - 1) *a.nc = excl + tot;
+        if (t == tiles - 1) {
+          // a union larger than the output's capacity keeps its first entries
+          // and raises the device status (capacity)
+          const uint64_t nc = excl + tot;
+          if (nc > a.nc_max) atomicOr(&g_status, 2);
+          *a.nc = min(nc, a.nc_max);
+        }
       }
     }
     __syncthreads();  // everyone is done reading s_k / s_c
@@ -1452,7 +1458,8 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
     }
     __syncthreads();
     const uint64_t L0 = s_L0;
-    for (uint32_t i = tid; i < tot; i += BLOCK) {
+    const uint32_t room = L0 < a.nc_max ? (uint32_t)min((uint64_t)tot, a.nc_max - L0) : 0u;
+    for (uint32_t i = tid; i < room; i += BLOCK) {
       a.kc[L0 + i] = s_k[i];
       a.cc[L0 + i] = s_c[i];
     }

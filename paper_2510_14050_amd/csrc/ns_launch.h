@@ -175,6 +175,7 @@ struct MergeArgs {
   const uint64_t *kb, *cb, *nb;
   uint64_t na_max, nb_max;  // host bounds on *na, *nb
   uint64_t *kc, *cc, *nc;
+  uint64_t nc_max;  // capacity of kc / cc: entries past it are dropped and flagged
   int sign;
   uint64_t *lb;   // [tiles]
   uint32_t *ticket;

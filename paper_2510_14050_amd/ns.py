@@ -63,6 +63,7 @@ class BatchMatricesView(ctypes.Structure):
 
 
 EXPORTS = ("ns_workspace_size", "ns_build_matrix", "ns_accumulate", "ns_stats",
+           "ns_stream_workspace_size", "ns_build_matrix_streamed",
            "ns_batch_stats", "ns_batch_stats_eager", "ns_max_link_packets",
            "ns_batch_max_link_packets", "ns_rolling_size", "ns_rolling_init",
            "ns_rolling_update", "ns_rolling_compact", "ns_device_status", "ns_release_graphs",
@@ -95,6 +96,8 @@ def load(path: str = LIB_PATH):
     lib.ns_workspace_size.argtypes = [U64, U32, ctypes.POINTER(U64)]
     lib.ns_build_matrix.argtypes = [P, P, U64, PM, P, U64, P]
     lib.ns_accumulate.argtypes = [PM, PM, I, PM, P, U64, P]
+    lib.ns_stream_workspace_size.argtypes = [U64, U64, ctypes.POINTER(U64)]
+    lib.ns_build_matrix_streamed.argtypes = [P, P, U64, U64, PM, P, U64, P, P]
     lib.ns_stats.argtypes = [PM, P, P, U64, P]
     batch = [P, P, P, U32, U64, P, PM, P, ctypes.POINTER(BatchMatricesView),
              ctypes.POINTER(Tuning), P, U64, P]
@@ -222,6 +225,48 @@ def build_matrix(src, dst, out: Matrix, ws: Workspace, stream=None) -> Matrix:
     v = out.view()
     _check(load().ns_build_matrix(_ptr(src), _ptr(dst), n, ctypes.byref(v), ws.ptr, ws.nbytes,
                                   _stream(stream)), "ns_build_matrix")
+    out.packets = int(v.packets)
+    return out
+
+
+def stream_workspace_size(batch: int, capacity: int) -> int:
+    out = ctypes.c_uint64()
+    _check(load().ns_stream_workspace_size(int(batch), int(capacity), ctypes.byref(out)),
+           "ns_stream_workspace_size")
+    return int(out.value)
+
+
+class StreamWorkspace:
+    """Device scratch memory of ns_build_matrix_streamed for sub-partitions of
+    `batch` packets and an aggregate of `capacity` links."""
+
+    def __init__(self, batch: int, capacity: int, device="cuda"):
+        torch = _torch()
+        self.batch, self.capacity = int(batch), int(capacity)
+        self.nbytes = stream_workspace_size(self.batch, self.capacity)
+        self.buf = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
+        assert self.buf.data_ptr() % 256 == 0
+
+    @property
+    def ptr(self):
+        return ctypes.c_void_p(self.buf.data_ptr())
+
+
+def build_matrix_streamed(src, dst, out: Matrix, ws: StreamWorkspace, stream=None,
+                          copy_stream=None) -> Matrix:
+    """ns_build_matrix_streamed: the matrix of host-resident packets (int32 CPU
+    tensors, pinned for overlap), built in sub-partitions of ws.batch packets."""
+    torch = _torch()
+    for x in (src, dst):
+        assert x.dtype == torch.int32 and not x.is_cuda and x.is_contiguous(), \
+            "int32 host contiguous"
+    n = src.numel()
+    assert dst.numel() == n
+    v = out.view()
+    cs = ctypes.c_void_p(copy_stream.cuda_stream) if copy_stream is not None else ctypes.c_void_p(0)
+    _check(load().ns_build_matrix_streamed(_ptr(src), _ptr(dst), n, ws.batch, ctypes.byref(v),
+                                           ws.ptr, ws.nbytes, _stream(stream), cs),
+           "ns_build_matrix_streamed")
     out.packets = int(v.packets)
     return out
 

@@ -100,3 +100,26 @@ def test_max_link_argument_errors(lib):
     assert lib.ns_batch_max_link_packets(ctypes.byref(wv), None, 4, 100, ctypes.c_void_p(256), None) == -1
     # capacity below the scanned positions
     assert lib.ns_batch_max_link_packets(ctypes.byref(wv), off, 4, 101, ctypes.c_void_p(256), None) == -2
+
+
+def test_streamed_build_argument_errors(lib):
+    """ns_build_matrix_streamed rejects bad arguments before any device call."""
+    out = ns.MatrixView(1024, 2048, 3072, 100, 0)
+    ws = ctypes.c_void_p(1 << 20)
+    host = ctypes.c_void_p(4096)
+    size = ctypes.c_uint64()
+    assert lib.ns_stream_workspace_size(0, 100, ctypes.byref(size)) == -1
+    assert lib.ns_stream_workspace_size(10, 100, None) == -1
+    assert lib.ns_stream_workspace_size(1000, 100, ctypes.byref(size)) == 0
+    small = size.value
+    assert lib.ns_stream_workspace_size(1000, 1 << 20, ctypes.byref(size)) == 0
+    assert size.value > small + 16 * ((1 << 20) - 100) * 0.99  # second aggregate buffer
+    args = lambda n, batch, o, w, nbytes: (host, host, n, batch, o, w, nbytes, None, None)
+    assert lib.ns_build_matrix_streamed(*args(10, 4, None, ws, 1 << 40)) == -1
+    assert lib.ns_build_matrix_streamed(None, None, 10, 4, ctypes.byref(out), ws, 1 << 40, None, None) == -1
+    assert lib.ns_build_matrix_streamed(*args(10, 0, ctypes.byref(out), ws, 1 << 40)) == -1
+    assert lib.ns_build_matrix_streamed(*args(10, 1 << 32, ctypes.byref(out), ws, 1 << 40)) == -6
+    tiny = ns.MatrixView(1024, 2048, 3072, 3, 0)  # below the first sub-partition
+    assert lib.ns_build_matrix_streamed(*args(10, 4, ctypes.byref(tiny), ws, 1 << 40)) == -2
+    assert lib.ns_build_matrix_streamed(*args(10, 4, ctypes.byref(out), ctypes.c_void_p(100), 1 << 40)) == -3
+    assert lib.ns_build_matrix_streamed(*args(10, 4, ctypes.byref(out), ws, 64)) == -3

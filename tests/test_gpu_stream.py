@@ -1,0 +1,124 @@
+"""Out-of-core build (Sec. III-C batching): host-resident packets streamed to
+the device in b_n sub-partitions and union-added; the result must equal the
+oracle's matrix of all packets bit for bit, whatever the batch size."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_14050_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    from paper_2510_14050_amd import ns
+    assert torch.cuda.is_available(), "GPU tests need a visible ROCm GPU"
+    ns.load()
+    return torch, ns
+
+
+def host32(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).pin_memory()
+
+
+def packets(seed, n, pool, s=1.2):
+    wl = synth.Workload("t", seed, pool, s, s + 0.1, np.array([n], np.int64))
+    return wl.window(0)
+
+
+def streamed(torch, ns, src, dst, batch, capacity, copy_stream=True):
+    out = ns.Matrix(capacity)
+    ws = ns.StreamWorkspace(batch, capacity)
+    cs = torch.cuda.Stream() if copy_stream else None
+    ns.build_matrix_streamed(host32(torch, src), host32(torch, dst), out, ws, copy_stream=cs)
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("batch", [200_003, 100_002, 65_536, 9_999, 4096, 1_000_000])
+def test_streamed_matches_oracle_for_every_batch_size(gpu, batch):
+    torch, ns = gpu
+    n = 200_003
+    say("streamed n", n, "batch", batch)
+    src, dst = packets(21, n, pool=3000)
+    ok, oc = oracle.build_matrix(src, dst)
+    out = streamed(torch, ns, src, dst, batch, n)
+    assert ns.device_status() == 0
+    k, c = out.numpy()
+    assert out.packets == n
+    assert np.array_equal(k, ok) and np.array_equal(c, oc)
+    st = torch.zeros(8, dtype=torch.int64, device="cuda")
+    ns.stats(out, st, ns.Workspace(n, 1))
+    torch.cuda.synchronize()
+    assert ns.stats_numpy(st).tolist() == oracle.stats(src, dst).tolist()
+
+
+@pytest.mark.parametrize("n,batch", [(0, 7), (1, 1), (5, 2), (4097, 4096), (3, 1000)])
+def test_streamed_small_and_empty(gpu, n, batch):
+    torch, ns = gpu
+    say("streamed small", n, batch)
+    src, dst = packets(22, n, pool=4) if n else (np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    out = streamed(torch, ns, src, dst, batch, max(n, 1), copy_stream=(n % 2 == 1))
+    assert ns.device_status() == 0
+    k, c = out.numpy()
+    ok, oc = oracle.build_matrix(src, dst)
+    assert np.array_equal(k, ok) and np.array_equal(c, oc)
+    assert out.packets == n
+
+
+def test_streamed_hot_links_across_batches(gpu):
+    """One link repeated through every sub-partition: counts add up across them."""
+    torch, ns = gpu
+    say("streamed hot link")
+    n = 50_000
+    src = np.full(n, 0xFFFFFFFF, np.uint32)
+    dst = np.zeros(n, np.uint32)
+    src[::7] = np.arange(src[::7].size, dtype=np.uint32)
+    out = streamed(torch, ns, src, dst, 3_001, n)
+    k, c = out.numpy()
+    ok, oc = oracle.build_matrix(src, dst)
+    assert np.array_equal(k, ok) and np.array_equal(c, oc)
+
+
+def test_streamed_capacity_overflow_is_reported_and_bounded(gpu):
+    """More links than the output holds: the device status says so and nothing
+    is written past the capacity."""
+    torch, ns = gpu
+    say("streamed overflow")
+    n = 40_000
+    src = np.arange(n, dtype=np.uint32)  # n distinct links
+    dst = np.arange(n, dtype=np.uint32) * 3
+    cap, guard = 25_000, 4096
+    keys = torch.full((cap + guard,), -7, dtype=torch.int64, device="cuda")
+    counts = torch.full((cap + guard,), -7, dtype=torch.int64, device="cuda")
+    nnz = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = ns.Matrix.wrap(keys, counts, nnz, cap, 0)
+    ws = ns.StreamWorkspace(10_000, cap)
+    ns.build_matrix_streamed(host32(torch, src), host32(torch, dst), out, ws)
+    assert ns.device_status() == -2
+    assert out.nnz() == cap
+    assert bool((keys[cap:] == -7).all()) and bool((counts[cap:] == -7).all())
+    ok, _ = oracle.build_matrix(src, dst)
+    assert np.array_equal(keys[:cap].cpu().numpy().view(np.uint64), ok[:cap])
+
+
+def test_streamed_workload_size(gpu):
+    """The 64-window workload's packets (8,388,608) from host memory in 2^21-packet
+    sub-partitions equal the oracle's aggregate matrix."""
+    torch, ns = gpu
+    wl = synth.WORKLOADS["windows64"]()
+    src, dst = wl.concat()
+    say("streamed windows64", src.size)
+    ok, oc = oracle.build_matrix(src, dst)
+    out = streamed(torch, ns, src, dst, 1 << 21, ok.size + 1024)
+    assert ns.device_status() == 0
+    k, c = out.numpy()
+    assert np.array_equal(k, ok) and np.array_equal(c, oc)
