@@ -418,8 +418,10 @@ def stream_leg(args, ns, torch, src_t, dst_t, agg, ws, dev):
     N = src_t.numel()
     src_h, dst_h = src_t.cpu().pin_memory(), dst_t.cpu().pin_memory()
     links = agg.nnz()
-    out = ns.Matrix(max(links, 1), device=dev)
     batch = min(args.stream_batch, max(N, 1))
+    # the first sub-partition is built in place in the output, so the
+    # capacity covers it as well as the aggregate's links
+    out = ns.Matrix(max(links, batch, 1), device=dev)
     sws = ns.StreamWorkspace(batch, out.capacity, device=dev)
     cs = torch.cuda.Stream(device=dev)
     reps = 5
