@@ -369,3 +369,16 @@ def test_workload_uneven1024(gpu):
     src, dst = wl.concat()
     res = run_batch(torch, ns, src, dst, list(wl.sizes), agg=False, win=False)
     check_batch(ns, src, dst, *res)
+
+
+def test_workload_uneven1024_with_aggregate(gpu):
+    """1024 uneven windows with their aggregate: the aggregate's 3.5 x 10^7 keys
+    take the chunked passes with more chunks than chunk-scan blocks (several
+    chunk rows per block); matrix and statistics against the oracle."""
+    torch, ns = gpu
+    say("workload uneven1024 + aggregate")
+    wl = synth.uneven1024()
+    src, dst = wl.concat()
+    assert src.size >= (1 << 24) and src.size > 1024 * 4 * 8192  # chunked, > 1024 chunks
+    res = run_batch(torch, ns, src, dst, list(wl.sizes), agg=True, win=False)
+    check_batch(ns, src, dst, *res)
