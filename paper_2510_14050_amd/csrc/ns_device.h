@@ -93,6 +93,14 @@ __device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *s_tmp,
   return pre + x - v;
 }
 
+// Load of a table that no kernel of the current launch writes (segment and
+// tile offsets), through the constant address space: with a uniform address
+// the compiler issues a scalar load, which completes on its own counter
+// instead of waiting behind the wave's outstanding vector loads and stores.
+__device__ __forceinline__ uint64_t ld_const(const uint64_t *p) {
+  return *(const __attribute__((address_space(4))) uint64_t *)(p);
+}
+
 // Index of the segment that owns tile t: the last w with off[w] <= t (empty
 // segments own no tiles, so this is never an empty one). Binary search; with t
 // uniform (in scalar registers) its loads are scalar and mostly hit the scalar
@@ -101,7 +109,7 @@ __device__ __forceinline__ uint32_t find_owner(const uint64_t *off, uint32_t W, 
   uint32_t lo = 0, hi = W;  // answer in [lo, hi)
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (off[mid] <= t) lo = mid; else hi = mid;
+    if (ld_const(off + mid) <= t) lo = mid; else hi = mid;
   }
   return lo;
 }
@@ -115,25 +123,25 @@ __device__ __forceinline__ uint32_t find_owner_near(const uint64_t *off, uint32_
   uint64_t lo, hi;  // off[lo] <= t < off[hi] (hi == W stands for +infinity)
   uint64_t g = t * W / total;
   if (g >= W) g = W - 1;
-  if (off[g] <= t) {
+  if (ld_const(off + g) <= t) {
     lo = g;
     for (uint64_t s = 1;; s <<= 1) {
       const uint64_t c = lo + s;
       if (c >= W) { hi = W; break; }
-      if (off[c] > t) { hi = c; break; }
+      if (ld_const(off + c) > t) { hi = c; break; }
       lo = c;
     }
   } else {
     hi = g;  // off[0] == 0 <= t, so this ends
     for (uint64_t s = 1;; s <<= 1) {
       const uint64_t c = hi > s ? hi - s : 0;
-      if (off[c] <= t) { lo = c; break; }
+      if (ld_const(off + c) <= t) { lo = c; break; }
       hi = c;
     }
   }
   while (hi - lo > 1) {
     const uint64_t mid = (lo + hi) >> 1;
-    if (off[mid] <= t) lo = mid; else hi = mid;
+    if (ld_const(off + mid) <= t) lo = mid; else hi = mid;
   }
   return (uint32_t)lo;
 }

@@ -137,7 +137,7 @@ __global__ __launch_bounds__(BLOCK) void k_hist(const uint32_t *__restrict__ src
   constexpr int ND = PACKETS ? kKeyDigits : kColDigits;
   constexpr int NC = ND * kBins;
   __shared__ uint32_t s_h[NC * C];
-  const uint64_t total = tile_off[W];
+  const uint64_t total = ld_const(tile_off + W);
   const uint64_t per = (total + gridDim.x - 1) / gridDim.x;
   const uint64_t t0 = (uint64_t)blockIdx.x * per, t1 = min(total, t0 + per);
   const uint32_t cp = threadIdx.x & (C - 1);
@@ -166,15 +166,15 @@ __global__ __launch_bounds__(BLOCK) void k_hist(const uint32_t *__restrict__ src
   uint32_t cur = t0 < t1 ? find_owner_wave(tile_off, W, t0) : 0;
   for (uint64_t t = t0; t < t1; ++t) {
     uint32_t w = cur;  // tiles come in order: step over finished (and empty) segments
-    while (tile_off[w + 1] <= t) ++w;
+    while (ld_const(tile_off + w + 1) <= t) ++w;
     if (w != cur) {  // uniform: every thread sees the same tile
       __syncthreads();
       flush(cur);
       __syncthreads();
       cur = w;
     }
-    const uint64_t start = seg_off[w] + (t - tile_off[w]) * (uint64_t)kHistTile;
-    const uint64_t end = min(start + (uint64_t)kHistTile, seg_off[w + 1]);
+    const uint64_t start = ld_const(seg_off + w) + (t - ld_const(tile_off + w)) * (uint64_t)kHistTile;
+    const uint64_t end = min(start + (uint64_t)kHistTile, ld_const(seg_off + w + 1));
     constexpr int R = 8;  // keys per thread per round, loads issued together
     for (uint64_t i0 = start + threadIdx.x; i0 < end; i0 += (uint64_t)R * BLOCK) {
       uint32_t lo[R], hi[R];
@@ -404,14 +404,22 @@ __device__ __forceinline__ uint32_t pass_ticket(const PassArgs &a, uint64_t laye
     const uint64_t k = (uint32_t)__builtin_amdgcn_readfirstlane(k0);
     if (k >= tickets) return 0xFFFFFFFFu;
     if (!layers) {
-      *seg = find_owner(a.tile_off, a.W, k);
+      // plain (vector) loads here: with thousands of windows, the scalar-cache
+      // search handed out tiles measurably faster and the passes ran slower
+      uint32_t lo = 0, hi = a.W;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.tile_off[mid] <= k) lo = mid; else hi = mid;
+      }
+      *seg = lo;
       return (uint32_t)k;
     }
     const uint32_t w = (uint32_t)(k % a.W);
     const uint64_t j = k / a.W;
-    if (a.tile_off[w] + j < a.tile_off[w + 1]) {
+    const uint64_t f = ld_const(a.tile_off + w);
+    if (f + j < ld_const(a.tile_off + w + 1)) {
       *seg = w;
-      return (uint32_t)(a.tile_off[w] + j);
+      return (uint32_t)(f + j);
     }
   }
 }
@@ -455,8 +463,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const uint32_t shift = a.shift;
-  const uint64_t layers = a.tile_off[a.W + 1];
-  const uint64_t tickets = layers ? (uint64_t)a.W * layers : a.tile_off[a.W];
+  const uint64_t layers = ld_const(a.tile_off + a.W + 1);
+  const uint64_t tickets = layers ? (uint64_t)a.W * layers : ld_const(a.tile_off + a.W);
   const uint32_t wbase = wv * (kWave * ITEMS);
   // Several segments: the keys of the next tile are requested before this
   // tile's look-back, so their memory latency overlaps the wait. One segment:
@@ -475,15 +483,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     }
   }
   __syncthreads();
-  uint32_t t = s_tile, w = s_seg;
+  uint32_t t = __builtin_amdgcn_readfirstlane(s_tile), w = __builtin_amdgcn_readfirstlane(s_seg);
   uint64_t seg_lo = 0;
   uint32_t first = 0, n = 0;
   uint64_t key[ITEMS];
   if (t != 0xFFFFFFFFu) {
-    first = (uint32_t)a.tile_off[w];
-    seg_lo = a.seg_off[w];
+    first = (uint32_t)ld_const(a.tile_off + w);
+    seg_lo = ld_const(a.seg_off + w);
     const uint64_t start = seg_lo + (uint64_t)(t - first) * TILE;
-    n = (uint32_t)min((uint64_t)TILE, a.seg_off[w + 1] - start);
+    n = (uint32_t)min((uint64_t)TILE, ld_const(a.seg_off + w + 1) - start);
     pass_load<ITEMS, PACKETS>(a, start, n, wbase, lane, TILE, key);
   }
 
@@ -516,13 +524,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     uint64_t seg_lo2 = 0;
     uint32_t first2 = 0, n2 = 0;
     if (pipe) {
-      t2 = s_tile;
-      w2 = s_seg;
+      t2 = __builtin_amdgcn_readfirstlane(s_tile);
+      w2 = __builtin_amdgcn_readfirstlane(s_seg);
       if (t2 != 0xFFFFFFFFu) {  // prefetch the next tile
-        first2 = (uint32_t)a.tile_off[w2];
-        seg_lo2 = a.seg_off[w2];
+        first2 = (uint32_t)ld_const(a.tile_off + w2);
+        seg_lo2 = ld_const(a.seg_off + w2);
         const uint64_t start2 = seg_lo2 + (uint64_t)(t2 - first2) * TILE;
-        n2 = (uint32_t)min((uint64_t)TILE, a.seg_off[w2 + 1] - start2);
+        n2 = (uint32_t)min((uint64_t)TILE, ld_const(a.seg_off + w2 + 1) - start2);
         pass_load<ITEMS, PACKETS>(a, start2, n2, wbase, lane, TILE, key);
       }
     }
@@ -547,13 +555,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     }
     __syncthreads();
     if (!pipe) {
-      t2 = s_tile;
-      w2 = s_seg;
+      t2 = __builtin_amdgcn_readfirstlane(s_tile);
+      w2 = __builtin_amdgcn_readfirstlane(s_seg);
       if (t2 != 0xFFFFFFFFu) {
-        first2 = (uint32_t)a.tile_off[w2];
-        seg_lo2 = a.seg_off[w2];
+        first2 = (uint32_t)ld_const(a.tile_off + w2);
+        seg_lo2 = ld_const(a.seg_off + w2);
         const uint64_t start2 = seg_lo2 + (uint64_t)(t2 - first2) * TILE;
-        n2 = (uint32_t)min((uint64_t)TILE, a.seg_off[w2 + 1] - start2);
+        n2 = (uint32_t)min((uint64_t)TILE, ld_const(a.seg_off + w2 + 1) - start2);
         pass_load<ITEMS, PACKETS>(a, start2, n2, wbase, lane, TILE, key);
       }
     }
@@ -583,8 +591,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void chunk_geometry(const ChunkArgs &c, uint32_t tile, uint64_t *lo,
                                                uint64_t *n, uint64_t *tiles, uint64_t *per) {
-  *lo = c.seg_off[0];
-  *n = c.seg_off[1] - c.seg_off[0];
+  *lo = ld_const(c.seg_off);
+  *n = ld_const(c.seg_off + 1) - *lo;
   *tiles = (*n + tile - 1) / tile;
   const uint64_t p = (*tiles + c.chunks - 1) / c.chunks;
   *per = p ? p : 1;
@@ -819,9 +827,9 @@ __device__ __forceinline__ ScanTile scan_tile(const uint64_t *tile_off, const ui
   g.n = 0;
   g.seg_lo = g.seg_hi = g.start = 0;
   if (g.t < total) {
-    g.first = (uint32_t)tile_off[g.w];
-    g.seg_lo = seg_off[g.w];
-    g.seg_hi = seg_off[g.w + 1];
+    g.first = (uint32_t)ld_const(tile_off + g.w);
+    g.seg_lo = ld_const(seg_off + g.w);
+    g.seg_hi = ld_const(seg_off + g.w + 1);
     g.start = g.seg_lo + (uint64_t)(g.t - g.first) * tile;
     g.n = (uint32_t)min((uint64_t)tile, g.seg_hi - g.start);
   }
@@ -890,7 +898,7 @@ void k_rle(RleArgs a) {
   __shared__ uint32_t s_next, s_next_w;
 
   const int tid = threadIdx.x, wv = tid / kWave;
-  const uint64_t total = a.tile_off[a.W];
+  const uint64_t total = ld_const(a.tile_off + a.W);
   const bool in_place = a.ukeys == a.keys;
   if (wv == 3) claim_tile(a.ticket, a.tile_off, a.W, total, &s_next, &s_next_w);
   __syncthreads();
@@ -1060,7 +1068,7 @@ void k_runs(RunArgs a) {
   __shared__ uint32_t s_next, s_next_w;
 
   const int tid = threadIdx.x, wv = tid / kWave;
-  const uint64_t total = a.tile_off[a.W];
+  const uint64_t total = ld_const(a.tile_off + a.W);
   if (wv == 3) claim_tile(a.ticket, a.tile_off, a.W, total, &s_next, &s_next_w);
   __syncthreads();
   ScanTile g = scan_tile(a.tile_off, a.seg_off, s_next, s_next_w, total, TILE);
