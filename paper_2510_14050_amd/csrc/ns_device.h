@@ -31,46 +31,73 @@ __device__ __forceinline__ uint64_t lb_load(const uint64_t *p) {
 
 // ---------------------------------------------------------------------------
 // wave / block helpers
+// Scans and reductions over the 64 lanes use DPP, which moves values between
+// lanes inside the VALU (no LDS round trip): row shifts by 1, 2, 4 and 8 scan
+// each row of 16 lanes, then the last lane of row 0 is broadcast into row 1
+// and of row 2 into row 3 (row_bcast:15), and lane 31 into rows 2 and 3
+// (row_bcast:31). Lanes whose source is outside the row, and rows left out by
+// the row mask, read 0. Every caller has all 64 lanes active.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, true);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint64_t dpp64(uint64_t x) {
+  const uint32_t lo = dpp32<CTRL, ROW_MASK>((uint32_t)x);
+  const uint32_t hi = dpp32<CTRL, ROW_MASK>((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <int CTRL, int ROW_MASK, typename T>
+__device__ __forceinline__ T dpp_mv(T v) {
+  if constexpr (sizeof(T) == 8) return dpp64<CTRL, ROW_MASK>(v);
+  else return dpp32<CTRL, ROW_MASK>(v);
+}
+
+// inclusive scan of x over lanes 0..lane with an associative op whose
+// identity is 0 (sum, max of unsigned values)
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_scan_dpp(T x, Op op) {
+  x = op(x, dpp_mv<kDppRowShr1, 0xf>(x));
+  x = op(x, dpp_mv<kDppRowShr2, 0xf>(x));
+  x = op(x, dpp_mv<kDppRowShr4, 0xf>(x));
+  x = op(x, dpp_mv<kDppRowShr8, 0xf>(x));
+  x = op(x, dpp_mv<kDppRowBcast15, 0xa>(x));
+  x = op(x, dpp_mv<kDppRowBcast31, 0xc>(x));
   return x;
 }
+
+__device__ __forceinline__ uint64_t lane63(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
+  return wave_scan_dpp<uint64_t>(x, [](uint64_t a, uint64_t b) { return a + b; });
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t x) {
+  return wave_scan_dpp<uint32_t>(x, [](uint32_t a, uint32_t b) { return a + b; });
+}
+
+// sum / maximum over the wave, returned in every lane
+__device__ __forceinline__ uint64_t wave_sum(uint64_t x) { return lane63(wave_incl_scan(x)); }
+
+__device__ __forceinline__ uint64_t wave_max(uint64_t x) {
+  return lane63(wave_scan_dpp<uint64_t>(x, [](uint64_t a, uint64_t b) { return a > b ? a : b; }));
+}
+
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 
 // number of set bits of m in lanes below this one
 __device__ __forceinline__ uint32_t count_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
-  const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    uint64_t y = __shfl_up(x, o, kWave);
-    if (lane >= o) x += y;
-  }
-  return x;
-}
-
-__device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t x) {
-  const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, kWave);
-    if (lane >= o) x += y;
-  }
-  return x;
-}
-
-__device__ __forceinline__ uint64_t wave_max(uint64_t x) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    uint64_t y = __shfl_xor(x, o, kWave);
-    x = x > y ? x : y;
-  }
-  return x;
 }
 
 // Block-wide exclusive scan of one u64 per thread. s_tmp holds BLOCK/64
