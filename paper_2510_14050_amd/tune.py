@@ -1,7 +1,7 @@
 """Autotuner for the batched path's launch shape.
 
 Sweeps the radix tile (256/512 threads x 8/16 keys) and the run-length /
-run-reduce tile (256 x 4/8 positions) on a given batch, timing graph replays of
+run-reduce tile (256 x 8/16 positions) on a given batch, timing graph replays of
 ns_batch_stats, and caches the fastest shape in a JSON file keyed by device
 name and size class (log2 of packets and of windows). Lookups fall back to
 the nearest cached size class of the same device, then to the library's
