@@ -163,6 +163,25 @@ int ns_build_matrix_streamed(const uint32_t *src, const uint32_t *dst, uint64_t 
  * into *out (device). m->packets must be below 2^32. */
 int ns_stats(const ns_matrix_t *m, ns_stats_t *out, void *ws, uint64_t ws_bytes, void *stream);
 
+/* The eight quantities of a matrix given in hypersparse CSR form, the form
+ * of the challenge's matrices (Sec. IV "Data Representation": the CSR is
+ * read as flat containers of its entries). All arrays are device memory:
+ *   rows     [nrows] source address of each stored row
+ *   row_ptr  [nrows+1] row r's entries are [row_ptr[r], row_ptr[r+1]);
+ *            row_ptr[0] = 0, row_ptr[nrows] = nnz
+ *   cols     [nnz] destination addresses, vals [nnz] A(i,j) >= 1
+ *   nnz      entries (host); packets = sum of vals (host bound, < 2^32)
+ * The keys rows[r]<<32 | cols[e] must increase strictly in entry order (rows
+ * ascending, columns ascending within a row); stored rows may be empty. An
+ * input that breaks this, holds a zero value, or whose row_ptr does not run
+ * from 0 to nnz is reported by ns_device_status (NS_ERR_INVALID_ARG) and
+ * gives undefined quantities; every read stays inside the arrays. Workspace:
+ * ns_stats_csr_workspace_size(nnz) bytes (it holds the flat entries). */
+int ns_stats_csr_workspace_size(uint64_t nnz, uint64_t *bytes);
+int ns_stats_csr(const uint32_t *rows, const uint64_t *row_ptr, uint64_t nrows,
+                 const uint32_t *cols, const uint64_t *vals, uint64_t nnz, uint64_t packets,
+                 ns_stats_t *out, void *ws, uint64_t ws_bytes, void *stream);
+
 /* Batched path: the eight quantities of each of num_windows windows in one
  * submission (captured once as a HIP graph and replayed; sizes are read from
  * device memory, so the graph holds for any window sizes within the bounds).
@@ -220,7 +239,8 @@ int ns_rolling_update(const ns_rolling_t *r, const ns_matrix_t *add, const ns_ma
 int ns_rolling_compact(const ns_rolling_t *from, const ns_rolling_t *to, void *stream);
 
 /* Synchronises `stream`, then reads and clears the current device's error
- * word: *status (host) = NS_OK, NS_ERR_UNDERFLOW or NS_ERR_CAPACITY. */
+ * word: *status (host) = NS_OK, NS_ERR_UNDERFLOW, NS_ERR_CAPACITY or
+ * NS_ERR_INVALID_ARG (a CSR input out of order), in that priority. */
 int ns_device_status(void *stream, int *status);
 
 /* Largest link count max_ij A(i,j) of a matrix: the "maximum link counts"

@@ -718,6 +718,36 @@ int ns_stats(const ns_matrix_t *m, ns_stats_t *out, void *ws, uint64_t ws_bytes,
   return enqueue_matrix_stats(w, sh, m, reinterpret_cast<uint64_t *>(out), s);
 }
 
+int ns_stats_csr_workspace_size(uint64_t nnz, uint64_t *bytes) {
+  if (!bytes) return NS_ERR_INVALID_ARG;
+  // the flat entries (keys, counts, nnz word), then the statistics' workspace
+  *bytes = up((2 * nnz + 1) * 8) + plan(nnz, 1).total;
+  return NS_OK;
+}
+
+int ns_stats_csr(const uint32_t *rows, const uint64_t *row_ptr, uint64_t nrows,
+                 const uint32_t *cols, const uint64_t *vals, uint64_t nnz, uint64_t packets,
+                 ns_stats_t *out, void *ws, uint64_t ws_bytes, void *stream) {
+  if (!out || !row_ptr) return NS_ERR_INVALID_ARG;
+  if (nnz > 0 && (!rows || !cols || !vals || nrows == 0)) return NS_ERR_INVALID_ARG;
+  if (packets < nnz) return NS_ERR_INVALID_ARG;  // every entry holds at least one packet
+  if (packets > kMaxPackets32) return NS_ERR_UNSUPPORTED;
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % kAlign) return NS_ERR_WORKSPACE;
+  const uint64_t flat = up((2 * nnz + 1) * 8);
+  if (ws_bytes < flat) return NS_ERR_WORKSPACE;
+  Ws w;
+  int rc = check_ws(static_cast<uint8_t *>(ws) + flat, ws_bytes - flat, nnz, 1, &w);
+  if (rc) return rc;
+  uint64_t *keys = static_cast<uint64_t *>(ws);
+  ns_matrix_t m{keys, keys + nnz, keys + 2 * nnz, nnz, packets};
+  Shapes sh;
+  resolve_tuning(nullptr, &sh);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(launch_csr_expand(rows, row_ptr, nrows, cols, vals, nnz, m.keys, m.counts, m.nnz, s));
+  HIP_TRY(launch_fill32(w.at<uint32_t>(w.L.tickets), kMaxTickets, 0, s));
+  return enqueue_matrix_stats(w, sh, &m, reinterpret_cast<uint64_t *>(out), s);
+}
+
 int ns_max_link_packets(const ns_matrix_t *m, uint64_t *out, void *stream) {
   if (!m || !out || !m->counts || !m->nnz) return NS_ERR_INVALID_ARG;
   const uint64_t cap = m->capacity < m->packets ? m->capacity : m->packets;

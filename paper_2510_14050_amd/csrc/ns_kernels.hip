@@ -25,7 +25,7 @@ constexpr int kHistBlock = NS_HIST_BLOCK;
 
 namespace ns {
 
-__device__ int g_status;  // bit 0: subtraction below zero; bit 1: a hash table is full
+__device__ int g_status;  // bit 0: subtraction below zero; bit 1: a capacity (hash table, merge output) is exceeded; bit 2: an input breaks its stated order
 
 // ---------------------------------------------------------------------------
 // small utilities
@@ -1174,6 +1174,60 @@ void k_runs(RunArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Hypersparse CSR to sorted COO (Sec. IV, "Data Representation": the
+// challenge's matrices come as CSR; the statistics here read the flat
+// entries). Row r (source address rows[r]) holds entries [row_ptr[r],
+// row_ptr[r+1]) of cols (destination addresses) and vals (A(i,j)); entry e
+// becomes key rows[r] << 32 | cols[e] with count vals[e]. Each thread expands
+// ITEMS consecutive entries: it bisects row_ptr for the row of its first
+// entry and then steps through the rows; every read stays inside the arrays
+// whatever their contents. Keys must increase strictly over the whole matrix,
+// values must be positive and row_ptr must run from 0 to nnz: a violation
+// raises the device status (invalid argument).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_csr_expand(const uint32_t *rows, const uint64_t *row_ptr,
+                                                    uint64_t nrows, const uint32_t *cols,
+                                                    const uint64_t *vals, uint64_t nnz,
+                                                    uint64_t *keys, uint64_t *counts,
+                                                    uint64_t *nnz_out) {
+  constexpr int ITEMS = 8;
+  const uint64_t e0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * ITEMS;
+  bool bad = false;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *nnz_out = nnz;
+    bad = row_ptr[0] != 0 || row_ptr[nrows] != nnz;
+  }
+  if (e0 < nnz) {
+    uint64_t lo = 0, hi = nrows;  // row of e0: the last r < nrows with row_ptr[r] <= e0
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (row_ptr[mid] <= e0) lo = mid; else hi = mid;
+    }
+    uint64_t r = lo, prev = 0;
+    bool has_prev = false;
+    if (e0 > 0) {  // the entry before this thread's first, for the order check
+      uint64_t rp = r;
+      while (rp > 0 && row_ptr[rp] > e0 - 1) --rp;
+      prev = ((uint64_t)rows[rp] << 32) | cols[e0 - 1];
+      has_prev = true;
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint64_t e = e0 + k;
+      if (e >= nnz) break;
+      while (r + 1 < nrows && row_ptr[r + 1] <= e) ++r;
+      const uint64_t key = ((uint64_t)rows[r] << 32) | cols[e], c = vals[e];
+      bad |= c == 0 || (has_prev && key <= prev);
+      prev = key;
+      has_prev = true;
+      keys[e] = key;
+      counts[e] = c;
+    }
+  }
+  if (bad) atomicOr(&g_status, 4);
+}
+
+// ---------------------------------------------------------------------------
 // Largest link count per window (Sec. IV, "Analytics and Operations": maximum
 // link counts). Window w's counts sit at [off[w], off[w] + nnz[w]) (the
 // positional layout of the batched per-window matrices); with off == nullptr
@@ -1731,6 +1785,17 @@ hipError_t launch_merge(const MergeArgs &a, uint64_t max_tiles, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_csr_expand(const uint32_t *rows, const uint64_t *row_ptr, uint64_t nrows,
+                             const uint32_t *cols, const uint64_t *vals, uint64_t nnz,
+                             uint64_t *keys, uint64_t *counts, uint64_t *nnz_out, hipStream_t s) {
+  const uint64_t per = 256ull * 8;
+  const uint64_t blocks = nnz ? (nnz + per - 1) / per : 1;
+  if (blocks > 0xFFFFFFFFull) return hipErrorInvalidValue;
+  NS_LAUNCH(k_csr_expand, dim3((uint32_t)blocks), dim3(256), s, rows, row_ptr, nrows, cols, vals,
+            nnz, keys, counts, nnz_out);
+  return hipGetLastError();
+}
+
 hipError_t read_and_clear_status(int *host_status) {
   int v = 0;
   hipError_t e = hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_status), sizeof(int), 0,
@@ -1738,7 +1803,7 @@ hipError_t read_and_clear_status(int *host_status) {
   if (e != hipSuccess) return e;
   const int zero = 0;
   e = hipMemcpyToSymbol(HIP_SYMBOL(g_status), &zero, sizeof(int), 0, hipMemcpyHostToDevice);
-  *host_status = (v & 1) ? -5 : (v & 2) ? -2 : 0;
+  *host_status = (v & 1) ? -5 : (v & 2) ? -2 : (v & 4) ? -1 : 0;
   return e;
 }
 

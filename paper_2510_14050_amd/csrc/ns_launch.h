@@ -182,6 +182,11 @@ struct MergeArgs {
 };
 hipError_t launch_merge(const MergeArgs &a, uint64_t max_tiles, hipStream_t s);
 
+// --- hypersparse CSR -> sorted COO (keys, counts); *nnz_out = nnz ---------------
+hipError_t launch_csr_expand(const uint32_t *rows, const uint64_t *row_ptr, uint64_t nrows,
+                             const uint32_t *cols, const uint64_t *vals, uint64_t nnz,
+                             uint64_t *keys, uint64_t *counts, uint64_t *nnz_out, hipStream_t s);
+
 // --- rolling aggregate (serving) ----------------------------------------------------
 struct RollHeader {
   uint64_t links, sources, dests, packets;  // live counts

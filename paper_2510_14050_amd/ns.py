@@ -64,6 +64,7 @@ class BatchMatricesView(ctypes.Structure):
 
 EXPORTS = ("ns_workspace_size", "ns_build_matrix", "ns_accumulate", "ns_stats",
            "ns_stream_workspace_size", "ns_build_matrix_streamed",
+           "ns_stats_csr_workspace_size", "ns_stats_csr",
            "ns_batch_stats", "ns_batch_stats_eager", "ns_max_link_packets",
            "ns_batch_max_link_packets", "ns_rolling_size", "ns_rolling_init",
            "ns_rolling_update", "ns_rolling_compact", "ns_device_status", "ns_release_graphs",
@@ -97,6 +98,8 @@ def load(path: str = LIB_PATH):
     lib.ns_build_matrix.argtypes = [P, P, U64, PM, P, U64, P]
     lib.ns_accumulate.argtypes = [PM, PM, I, PM, P, U64, P]
     lib.ns_stream_workspace_size.argtypes = [U64, U64, ctypes.POINTER(U64)]
+    lib.ns_stats_csr_workspace_size.argtypes = [U64, ctypes.POINTER(U64)]
+    lib.ns_stats_csr.argtypes = [P, P, U64, P, P, U64, U64, P, P, U64, P]
     lib.ns_build_matrix_streamed.argtypes = [P, P, U64, U64, PM, P, U64, P, P]
     lib.ns_stats.argtypes = [PM, P, P, U64, P]
     batch = [P, P, P, U32, U64, P, PM, P, ctypes.POINTER(BatchMatricesView),
@@ -287,6 +290,32 @@ def stats(m: Matrix, out, ws: Workspace, stream=None):
     assert out.numel() >= 8 and out.dtype.itemsize == 8
     _check(load().ns_stats(ctypes.byref(v), _ptr(out), ws.ptr, ws.nbytes, _stream(stream)),
            "ns_stats")
+    return out
+
+
+def stats_csr_workspace_size(nnz: int) -> int:
+    out = ctypes.c_uint64()
+    _check(load().ns_stats_csr_workspace_size(int(nnz), ctypes.byref(out)),
+           "ns_stats_csr_workspace_size")
+    return int(out.value)
+
+
+def stats_csr(rows, row_ptr, cols, vals, packets: int, out, ws=None, stream=None):
+    """ns_stats_csr: the eight quantities of a hypersparse CSR matrix (device
+    tensors: rows int32 [nrows] source addresses, row_ptr int64 [nrows+1],
+    cols int32 [nnz] destination addresses, vals int64 [nnz]) into `out`
+    (int64 cuda tensor of 8). `ws`: a uint8 cuda tensor of at least
+    stats_csr_workspace_size(nnz) bytes (allocated here when None)."""
+    torch = _torch()
+    nnz, nrows = cols.numel(), rows.numel()
+    assert vals.numel() == nnz and row_ptr.numel() == nrows + 1
+    need = stats_csr_workspace_size(nnz)
+    if ws is None:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=cols.device)
+    assert ws.numel() >= need and ws.data_ptr() % 256 == 0
+    _check(load().ns_stats_csr(_ptr(rows), _ptr(row_ptr), nrows, _ptr(cols), _ptr(vals), nnz,
+                               int(packets), _ptr(out), ctypes.c_void_p(ws.data_ptr()),
+                               ws.numel(), _stream(stream)), "ns_stats_csr")
     return out
 
 

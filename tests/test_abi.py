@@ -123,3 +123,22 @@ def test_streamed_build_argument_errors(lib):
     assert lib.ns_build_matrix_streamed(*args(10, 4, ctypes.byref(tiny), ws, 1 << 40)) == -2
     assert lib.ns_build_matrix_streamed(*args(10, 4, ctypes.byref(out), ctypes.c_void_p(100), 1 << 40)) == -3
     assert lib.ns_build_matrix_streamed(*args(10, 4, ctypes.byref(out), ws, 64)) == -3
+
+
+def test_stats_csr_argument_errors(lib):
+    """ns_stats_csr rejects bad arguments before any device call."""
+    size = ctypes.c_uint64()
+    assert lib.ns_stats_csr_workspace_size(100, None) == -1
+    assert lib.ns_stats_csr_workspace_size(100, ctypes.byref(size)) == 0
+    assert size.value >= 16 * 100
+    p = ctypes.c_void_p(4096)
+    ws = ctypes.c_void_p(1 << 20)
+    # rows, row_ptr, nrows, cols, vals, nnz, packets, out, ws, ws_bytes, stream
+    assert lib.ns_stats_csr(p, p, 1, p, p, 4, 4, None, ws, 1 << 40, None) == -1   # no output
+    assert lib.ns_stats_csr(p, None, 1, p, p, 4, 4, p, ws, 1 << 40, None) == -1   # no row_ptr
+    assert lib.ns_stats_csr(p, p, 0, p, p, 4, 4, p, ws, 1 << 40, None) == -1      # entries, no rows
+    assert lib.ns_stats_csr(p, p, 1, None, p, 4, 4, p, ws, 1 << 40, None) == -1
+    assert lib.ns_stats_csr(p, p, 1, p, p, 4, 3, p, ws, 1 << 40, None) == -1      # packets < nnz
+    assert lib.ns_stats_csr(p, p, 1, p, p, 4, 1 << 32, p, ws, 1 << 40, None) == -6
+    assert lib.ns_stats_csr(p, p, 1, p, p, 4, 4, p, ctypes.c_void_p(100), 1 << 40, None) == -3
+    assert lib.ns_stats_csr(p, p, 1, p, p, 4, 4, p, ws, 64, None) == -3
