@@ -169,13 +169,14 @@ int ns_stats(const ns_matrix_t *m, ns_stats_t *out, void *ws, uint64_t ws_bytes,
  *   rows     [nrows] source address of each stored row
  *   row_ptr  [nrows+1] row r's entries are [row_ptr[r], row_ptr[r+1]);
  *            row_ptr[0] = 0, row_ptr[nrows] = nnz
- *   cols     [nnz] destination addresses, vals [nnz] A(i,j) >= 1
+ *   cols     [nnz] destination addresses, vals [nnz] A(i,j), 1 <= A(i,j) < 2^32
  *   nnz      entries (host); packets = sum of vals (host bound, < 2^32)
  * The keys rows[r]<<32 | cols[e] must increase strictly in entry order (rows
  * ascending, columns ascending within a row); stored rows may be empty. An
- * input that breaks this, holds a zero value, or whose row_ptr does not run
- * from 0 to nnz is reported by ns_device_status (NS_ERR_INVALID_ARG) and
- * gives undefined quantities; every read stays inside the arrays. Workspace:
+ * input that breaks this, holds a value outside [1, 2^32), whose values sum
+ * to more than `packets`, or whose row_ptr does not run from 0 to nnz is
+ * reported by ns_device_status (NS_ERR_INVALID_ARG) and gives undefined
+ * quantities; every read stays inside the arrays. Workspace:
  * ns_stats_csr_workspace_size(nnz) bytes (it holds the flat entries). */
 int ns_stats_csr_workspace_size(uint64_t nnz, uint64_t *bytes);
 int ns_stats_csr(const uint32_t *rows, const uint64_t *row_ptr, uint64_t nrows,

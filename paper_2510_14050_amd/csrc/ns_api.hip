@@ -745,7 +745,11 @@ int ns_stats_csr(const uint32_t *rows, const uint64_t *row_ptr, uint64_t nrows,
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_TRY(launch_csr_expand(rows, row_ptr, nrows, cols, vals, nnz, m.keys, m.counts, m.nnz, s));
   HIP_TRY(launch_fill32(w.at<uint32_t>(w.L.tickets), kMaxTickets, 0, s));
-  return enqueue_matrix_stats(w, sh, &m, reinterpret_cast<uint64_t *>(out), s);
+  rc = enqueue_matrix_stats(w, sh, &m, reinterpret_cast<uint64_t *>(out), s);
+  if (rc) return rc;
+  // the values' sum (valid packets) may not pass the caller's bound
+  HIP_TRY(launch_check_total(reinterpret_cast<const uint64_t *>(out), packets, s));
+  return NS_OK;
 }
 
 int ns_max_link_packets(const ns_matrix_t *m, uint64_t *out, void *stream) {

@@ -1182,8 +1182,9 @@ void k_runs(RunArgs a) {
 // ITEMS consecutive entries: it bisects row_ptr for the row of its first
 // entry and then steps through the rows; every read stays inside the arrays
 // whatever their contents. Keys must increase strictly over the whole matrix,
-// values must be positive and row_ptr must run from 0 to nnz: a violation
-// raises the device status (invalid argument).
+// values must lie in [1, 2^32) (the column items hold a count in 32 bits; with
+// fewer than 2^32 entries their sum then cannot wrap) and row_ptr must run
+// from 0 to nnz: a violation raises the device status (invalid argument).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_csr_expand(const uint32_t *rows, const uint64_t *row_ptr,
                                                     uint64_t nrows, const uint32_t *cols,
@@ -1217,7 +1218,7 @@ __global__ __launch_bounds__(256) void k_csr_expand(const uint32_t *rows, const 
       if (e >= nnz) break;
       while (r + 1 < nrows && row_ptr[r + 1] <= e) ++r;
       const uint64_t key = ((uint64_t)rows[r] << 32) | cols[e], c = vals[e];
-      bad |= c == 0 || (has_prev && key <= prev);
+      bad |= c == 0 || (c >> 32) != 0 || (has_prev && key <= prev);
       prev = key;
       has_prev = true;
       keys[e] = key;
@@ -1225,6 +1226,13 @@ __global__ __launch_bounds__(256) void k_csr_expand(const uint32_t *rows, const 
     }
   }
   if (bad) atomicOr(&g_status, 4);
+}
+
+// The packet total of a CSR input (its valid packets, stats[0], the sum of
+// the values) against the caller's bound on it: a larger sum raises the device
+// status (invalid argument).
+__global__ void k_check_total(const uint64_t *stats, uint64_t packets) {
+  if (threadIdx.x == 0 && stats[0] > packets) atomicOr(&g_status, 4);
 }
 
 // ---------------------------------------------------------------------------
@@ -1793,6 +1801,11 @@ hipError_t launch_csr_expand(const uint32_t *rows, const uint64_t *row_ptr, uint
   if (blocks > 0xFFFFFFFFull) return hipErrorInvalidValue;
   NS_LAUNCH(k_csr_expand, dim3((uint32_t)blocks), dim3(256), s, rows, row_ptr, nrows, cols, vals,
             nnz, keys, counts, nnz_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_total(const uint64_t *stats, uint64_t packets, hipStream_t s) {
+  NS_LAUNCH(k_check_total, dim3(1), dim3(kWave), s, stats, packets);
   return hipGetLastError();
 }
 

@@ -186,6 +186,8 @@ hipError_t launch_merge(const MergeArgs &a, uint64_t max_tiles, hipStream_t s);
 hipError_t launch_csr_expand(const uint32_t *rows, const uint64_t *row_ptr, uint64_t nrows,
                              const uint32_t *cols, const uint64_t *vals, uint64_t nnz,
                              uint64_t *keys, uint64_t *counts, uint64_t *nnz_out, hipStream_t s);
+// Raises the device status when stats[0] (valid packets) exceeds `packets`.
+hipError_t launch_check_total(const uint64_t *stats, uint64_t packets, hipStream_t s);
 
 // --- rolling aggregate (serving) ----------------------------------------------------
 struct RollHeader {

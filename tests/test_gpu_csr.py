@@ -123,3 +123,36 @@ def test_csr_bad_input_is_reported(gpu):
     run_csr(torch, ns, rows, short, cols, vals, src.size)
     assert ns.device_status() == -1
     assert ns.device_status() == 0  # reading clears the word
+
+
+def test_csr_value_range_and_total_are_checked(gpu):
+    """Values must lie in [1, 2^32) and sum to at most the caller's packet
+    bound: a value of 2^32, two values whose 64-bit sum wraps around, a sum
+    past the bound and keys out of order each raise the device status, while
+    a bound equal to the sum is accepted."""
+    torch, ns = gpu
+    say("csr value range and packet total")
+    src, dst = packets(34, 3000, 60)
+    k, c = oracle.build_matrix(src, dst)
+    rows, row_ptr, cols, vals = to_csr(k, c)
+    assert c.max() > 1 and k.size < src.size
+    big = vals.copy()
+    big[1] = np.uint64(1 << 32)
+    run_csr(torch, ns, rows, row_ptr, cols, big, src.size)
+    assert ns.device_status() == -1
+    wrap = vals.copy()
+    wrap[0] = wrap[-1] = np.uint64(1 << 63)  # the sum wraps to below the bound
+    run_csr(torch, ns, rows, row_ptr, cols, wrap, src.size)
+    assert ns.device_status() == -1
+    run_csr(torch, ns, rows, row_ptr, cols, vals, k.size)  # nnz <= bound < sum
+    assert ns.device_status() == -1
+    r = int(np.argmax(np.diff(row_ptr.astype(np.int64)) >= 2))
+    e = int(row_ptr[r])
+    assert row_ptr[r + 1] - row_ptr[r] >= 2
+    swapped = cols.copy()
+    swapped[e], swapped[e + 1] = cols[e + 1], cols[e]
+    run_csr(torch, ns, rows, row_ptr, swapped, vals, src.size)
+    assert ns.device_status() == -1
+    got = run_csr(torch, ns, rows, row_ptr, cols, vals, int(c.sum()))
+    assert ns.device_status() == 0
+    assert got == oracle.stats_matrix(k, c).tolist()
