@@ -1640,15 +1640,22 @@ hipError_t launch_tiles(const uint64_t *seg_off, uint32_t W, uint32_t ta, uint64
   return hipGetLastError();
 }
 
+// Histogram workgroups: four tiles each, since every flush of a workgroup's
+// counters costs one global atomic per bin and fewer, longer ranges cost fewer
+// atomics; but at least one tile each up to 64 workgroups, so that a small
+// batch is not counted by a handful of workgroups.
+static uint64_t hist_blocks(uint64_t tiles) {
+  const uint64_t four = (tiles + 3) / 4, floor = tiles < 64 ? tiles : 64;
+  return four > floor ? four : floor;
+}
+
 hipError_t launch_hist_packets(const uint32_t *src, const uint32_t *dst, const uint64_t *seg_off,
                                const uint64_t *tile_off, uint32_t W, uint64_t max_tiles,
                                uint32_t *hist, hipStream_t s) {
   static uint64_t cap[64];
   const int d = device_id();
   if (!cap[d]) cap[d] = resident(k_hist<kHistBlock, true>, kHistBlock);
-  // at least four tiles per workgroup: each flush of a workgroup's counters
-  // costs one global atomic per bin, so fewer, longer ranges cost fewer atomics
-  NS_LAUNCH((k_hist<kHistBlock, true>), dim3(clamp_grid((max_tiles + 3) / 4, cap[d])), dim3(kHistBlock), s, src, dst,
+  NS_LAUNCH((k_hist<kHistBlock, true>), dim3(clamp_grid(hist_blocks(max_tiles), cap[d])), dim3(kHistBlock), s, src, dst,
             nullptr, seg_off, tile_off, W, hist);
   return hipGetLastError();
 }
@@ -1659,7 +1666,7 @@ hipError_t launch_hist_items(const uint64_t *items, const uint64_t *seg_off,
   static uint64_t cap[64];
   const int d = device_id();
   if (!cap[d]) cap[d] = resident(k_hist<kHistBlock, false>, kHistBlock);
-  NS_LAUNCH((k_hist<kHistBlock, false>), dim3(clamp_grid((max_tiles + 3) / 4, cap[d])), dim3(kHistBlock), s, nullptr,
+  NS_LAUNCH((k_hist<kHistBlock, false>), dim3(clamp_grid(hist_blocks(max_tiles), cap[d])), dim3(kHistBlock), s, nullptr,
             nullptr, items, seg_off, tile_off, W, hist);
   return hipGetLastError();
 }
