@@ -40,7 +40,7 @@ def parse():
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="target CPU time of the oracle baseline sample")
-    p.add_argument("--serve-arrivals", type=int, default=3072,
+    p.add_argument("--serve-arrivals", type=int, default=11024,
                    help="serving leg: arrivals (the first --serve-warm are warm-up); 0 = skip")
     p.add_argument("--serve-warm", type=int, default=1024)
     p.add_argument("--serve-rate", type=float, default=2000.0)
