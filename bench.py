@@ -64,7 +64,8 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this path runs on a single GPU; multi-GPU runs are not supported "
-              "(see DESIGN.md, 'Sharding')", file=sys.stderr)
+              "(windows would shard across GPUs and the aggregate by a hash of its rows and "
+              "columns, but neither exchange is built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
