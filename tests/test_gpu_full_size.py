@@ -1,5 +1,6 @@
-"""Full-size check of the 2^30-packet aggregate (8192 windows of 2^17 with a
-scanner and a sink), in the benchmark's launch configuration.
+"""Full-size checks: the 2^30-packet aggregate (8192 windows of 2^17 with a
+scanner and a sink) in the benchmark's launch configuration, and one window
+past 2^31 packets with a closed-form answer.
 
 The oracle cannot sort 2^30 keys within a test's time, so parity here is:
 * properties that hold at any size (sorted strictly increasing keys, counts
@@ -85,3 +86,56 @@ def test_aggregate_2p30_full_size():
     srow = keys[rows == np.uint64(wl.scanner)]
     assert srow.size == 1 << 16
     assert int(counts[rows == np.uint64(wl.scanner)].sum()) == 8192 * wl.scan_count(1 << 17)
+
+
+def test_single_window_past_2p31_packets():
+    """One window of 2^31 + 12345 packets, past the signed 32-bit range of
+    positions, through the chunked single-segment sort. Packet i' (i' = a fixed
+    bijection of the index) is source 0x9E370000 + (i' mod 2^16), destination
+    0x7F000000 + ((i' >> 16) mod 2^15): every one of the 2^31 (source,
+    destination) pairs once, and the 12345 packets past 2^31 repeat the pairs
+    (s, 0) for s < 12345. The eight quantities, the largest link count and
+    every entry of the matrix follow in closed form (no oracle run needed)."""
+    import torch
+    from paper_2510_14050_amd import ns
+    dev = torch.device("cuda:0")
+    torch.cuda.empty_cache()
+    r = 12345
+    N = (1 << 31) + r
+    mult = 1_000_000_007  # prime, does not divide N: i -> i * mult mod N is a bijection
+    assert N % mult != 0
+    say("generating", N, "packets on the device")
+    i = torch.arange(N, dtype=torch.int64, device=dev)
+    i.mul_(mult).remainder_(N)
+    src_t = ((i & 0xFFFF) + (0x9E370000 - (1 << 32))).to(torch.int32)
+    dst_t = (((i >> 16) & 0x7FFF) + 0x7F000000).to(torch.int32)
+    del i
+    torch.cuda.empty_cache()
+    ws = ns.Workspace(N, 1, device=dev)
+    m = ns.Matrix(N, device=dev)
+    st = torch.zeros(8, dtype=torch.int64, device=dev)
+    ml = torch.zeros(1, dtype=torch.int64, device=dev)
+    say("ns_build_matrix + ns_stats + ns_max_link_packets")
+    ns.build_matrix(src_t, dst_t, m, ws)
+    ns.stats(m, st, ws)
+    ns.max_link_packets(m, ml)
+    torch.cuda.synchronize()
+    assert ns.device_status() == 0
+    got = [int(x) for x in ns.stats_numpy(st)]
+    say("stats", got, "max link", int(ml.item()))
+    L = 1 << 31
+    assert got == [N, L, 1 << 16, 1 << 15, (1 << 15) + 1, 1 << 15, (1 << 16) + r, 1 << 16]
+    assert int(ml.item()) == 2
+    assert m.nnz() == L
+    say("matrix against its closed form, in chunks")
+    step = 1 << 27
+    for k0 in range(0, L, step):
+        k = torch.arange(k0, k0 + step, dtype=torch.int64, device=dev)
+        s, d = k >> 15, k & 0x7FFF
+        # the key's bit pattern as int64: (source - 2^32) * 2^32 + destination
+        want = (s + (0x9E370000 - (1 << 32))) * (1 << 32) + (d + 0x7F000000)
+        assert torch.equal(m.keys[k0:k0 + step], want), k0
+        want_c = 1 + ((d == 0) & (s < r)).to(torch.int64)
+        assert torch.equal(m.counts[k0:k0 + step], want_c), k0
+    del ws, m, src_t, dst_t
+    torch.cuda.empty_cache()
