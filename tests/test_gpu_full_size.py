@@ -1,6 +1,6 @@
 """Full-size checks: the 2^30-packet aggregate (8192 windows of 2^17 with a
-scanner and a sink) in the benchmark's launch configuration, and one window
-past 2^31 packets with a closed-form answer.
+scanner and a sink) in the benchmark's launch configuration, and past 2^31
+packets one window and a batch of 32769 windows with closed-form answers.
 
 The oracle cannot sort 2^30 keys within a test's time, so parity here is:
 * properties that hold at any size (sorted strictly increasing keys, counts
@@ -138,4 +138,58 @@ def test_single_window_past_2p31_packets():
         want_c = 1 + ((d == 0) & (s < r)).to(torch.int64)
         assert torch.equal(m.counts[k0:k0 + step], want_c), k0
     del ws, m, src_t, dst_t
+    torch.cuda.empty_cache()
+
+
+def test_batch_past_2p31_packets():
+    """The same 2^31 + 12345 pairs as above, as a batch of 32769 windows with
+    their aggregate: window w < 2^15 holds packets [w * 2^16, (w + 1) * 2^16),
+    all to destination w, from the 2^16 sources in a scrambled order (index j
+    of the window -> source j * 40503 mod 2^16); the last window holds the
+    12345 packets past 2^31, all to destination 0. Every window's quantities,
+    the aggregate's and all 2^31 aggregate entries follow in closed form."""
+    import torch
+    from paper_2510_14050_amd import ns
+    dev = torch.device("cuda:0")
+    torch.cuda.empty_cache()
+    r = 12345
+    N = (1 << 31) + r
+    W = (1 << 15) + 1
+    say("generating", N, "packets in", W, "windows on the device")
+    i = torch.arange(N, dtype=torch.int64, device=dev)
+    src_t = ((((i & 0xFFFF) * 40503) & 0xFFFF) + (0x9E370000 - (1 << 32))).to(torch.int32)
+    dst_t = (((i >> 16) & 0x7FFF) + 0x7F000000).to(torch.int32)
+    del i
+    torch.cuda.empty_cache()
+    off = torch.arange(W + 1, dtype=torch.int64, device=dev) * (1 << 16)
+    off[-1] = N
+    ws = ns.Workspace(N, W, device=dev)
+    agg = ns.Matrix(N, device=dev)
+    st = torch.zeros(8, dtype=torch.int64, device=dev)
+    win_st = torch.zeros((W, 8), dtype=torch.int64, device=dev)
+    say("ns_batch_stats:", W, "windows + aggregate")
+    ns.batch_stats(src_t, dst_t, off, win_st, ws, agg=agg, agg_stats=st)
+    torch.cuda.synchronize()
+    assert ns.device_status() == 0
+    per = ns.stats_numpy(win_st).astype(np.int64)
+    full = np.array([1 << 16, 1 << 16, 1 << 16, 1, 1, 1, 1 << 16, 1 << 16], np.int64)
+    assert np.array_equal(per[:-1], np.broadcast_to(full, (W - 1, 8)))
+    assert per[-1].tolist() == [r, r, r, 1, 1, 1, r, r]
+    got = [int(x) for x in ns.stats_numpy(st)]
+    say("aggregate stats", got)
+    L = 1 << 31
+    assert got == [N, L, 1 << 16, 1 << 15, (1 << 15) + 1, 1 << 15, (1 << 16) + r, 1 << 16]
+    assert agg.nnz() == L
+    twice = torch.zeros(1 << 16, dtype=torch.bool, device=dev)  # sources of the last window
+    twice[(torch.arange(r, dtype=torch.int64, device=dev) * 40503) & 0xFFFF] = True
+    say("aggregate matrix against its closed form, in chunks")
+    step = 1 << 27
+    for k0 in range(0, L, step):
+        k = torch.arange(k0, k0 + step, dtype=torch.int64, device=dev)
+        s, d = k >> 15, k & 0x7FFF
+        want = (s + (0x9E370000 - (1 << 32))) * (1 << 32) + (d + 0x7F000000)
+        assert torch.equal(agg.keys[k0:k0 + step], want), k0
+        want_c = 1 + ((d == 0) & twice[s]).to(torch.int64)
+        assert torch.equal(agg.counts[k0:k0 + step], want_c), k0
+    del ws, agg, src_t, dst_t, win_st
     torch.cuda.empty_cache()
