@@ -1,6 +1,7 @@
 """Full-size checks: the 2^30-packet aggregate (8192 windows of 2^17 with a
-scanner and a sink) in the benchmark's launch configuration, and past 2^31
-packets one window and a batch of 32769 windows with closed-form answers.
+scanner and a sink) in the benchmark's launch configuration; and, past 2^31
+packets or entries, one window, a batch of 32769 windows and a union-add, all
+with closed-form answers.
 
 The oracle cannot sort 2^30 keys within a test's time, so parity here is:
 * properties that hold at any size (sorted strictly increasing keys, counts
@@ -192,4 +193,61 @@ def test_batch_past_2p31_packets():
         want_c = 1 + ((d == 0) & twice[s]).to(torch.int64)
         assert torch.equal(agg.counts[k0:k0 + step], want_c), k0
     del ws, agg, src_t, dst_t, win_st
+    torch.cuda.empty_cache()
+
+
+def test_union_add_past_2p31_entries():
+    """ns_accumulate of two sorted matrices whose union holds 2^31 entries:
+    A = every (s, d) with d even (2^30 entries, count 1), B = every (s, d) with
+    d odd plus (s, 0) for s < 12345 (count 1). A + B is every pair of 2^16
+    sources x 2^15 destinations, count 2 at (s, 0) for s < 12345; its
+    statistics follow in closed form as well."""
+    import torch
+    from paper_2510_14050_amd import ns
+    dev = torch.device("cuda:0")
+    torch.cuda.empty_cache()
+    r = 12345
+    half = 1 << 30
+
+    def key(s, d):
+        return (s + (0x9E370000 - (1 << 32))) * (1 << 32) + (d + 0x7F000000)
+
+    say("building A (2^30 entries) and B (2^30 + 12345 entries) on the device")
+    e = torch.arange(half, dtype=torch.int64, device=dev)
+    s, m = e >> 14, e & 0x3FFF
+    A = ns.Matrix.wrap(key(s, 2 * m), torch.ones(half, dtype=torch.int64, device=dev),
+                       torch.tensor([half], dtype=torch.int64, device=dev), half, half)
+    nb = half + r
+    kb = torch.empty(nb, dtype=torch.int64, device=dev)
+    # row s of B: (s, 0) first when s < r, then its odd destinations
+    kb[e + torch.clamp(s + 1, max=r)] = key(s, 2 * m + 1)
+    del e, s, m
+    xs = torch.arange(r, dtype=torch.int64, device=dev)
+    kb[xs * (1 << 14) + xs] = key(xs, torch.zeros_like(xs))
+    B = ns.Matrix.wrap(kb, torch.ones(nb, dtype=torch.int64, device=dev),
+                       torch.tensor([nb], dtype=torch.int64, device=dev), nb, nb)
+    torch.cuda.empty_cache()
+    N = half + nb
+    ws = ns.Workspace(N, 1, device=dev)
+    C = ns.Matrix(N, device=dev)
+    st = torch.zeros(8, dtype=torch.int64, device=dev)
+    say("ns_accumulate A + B, then ns_stats")
+    ns.accumulate(A, B, 1, C, ws)
+    ns.stats(C, st, ws)
+    torch.cuda.synchronize()
+    assert ns.device_status() == 0
+    L = 1 << 31
+    assert C.nnz() == L and C.packets == N
+    got = [int(x) for x in ns.stats_numpy(st)]
+    say("stats", got)
+    assert got == [N, L, 1 << 16, 1 << 15, (1 << 15) + 1, 1 << 15, (1 << 16) + r, 1 << 16]
+    say("union against its closed form, in chunks")
+    step = 1 << 27
+    for k0 in range(0, L, step):
+        k = torch.arange(k0, k0 + step, dtype=torch.int64, device=dev)
+        s, d = k >> 15, k & 0x7FFF
+        assert torch.equal(C.keys[k0:k0 + step], key(s, d)), k0
+        want_c = 1 + ((d == 0) & (s < r)).to(torch.int64)
+        assert torch.equal(C.counts[k0:k0 + step], want_c), k0
+    del A, B, C, ws, kb
     torch.cuda.empty_cache()
