@@ -129,7 +129,12 @@ int ns_build_matrix(const uint32_t *src, const uint32_t *dst, uint64_t n, ns_mat
  * cap, win packets) for add, >= min(acc_in cap, acc_in packets) for subtract.
  * Subtracting more packets than acc_in holds is rejected on the host; an
  * entry of win that is absent from or larger than acc_in is detected on the
- * device and reported by ns_device_status (acc_out is then undefined). */
+ * device and reported by ns_device_status (acc_out is then undefined).
+ * Workspace: ns_accumulate_workspace_size(na, nb) bytes, 256-byte aligned,
+ * with na = min(acc_in cap, acc_in packets) and nb = min(win cap, win
+ * packets) (a few bytes per thousand entries; a workspace of
+ * ns_workspace_size(na + nb, 1) bytes is also large enough). */
+int ns_accumulate_workspace_size(uint64_t na, uint64_t nb, uint64_t *bytes);
 int ns_accumulate(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
                   ns_matrix_t *acc_out, void *ws, uint64_t ws_bytes, void *stream);
 

@@ -138,6 +138,20 @@ StreamLayout stream_plan(uint64_t batch, uint64_t capacity) {
   return L;
 }
 
+// Workspace of a union-add of at most n entries: the merge tiles' ticket,
+// then one look-back word per merge tile.
+struct MergeLayout {
+  uint64_t lbs, tiles, total;
+};
+
+MergeLayout merge_plan(uint64_t n) {
+  MergeLayout L{};
+  L.tiles = n / kMergeTile + 2;
+  L.lbs = up(4);
+  L.total = L.lbs + up(L.tiles * 8);
+  return L;
+}
+
 #define HIP_TRY(expr)                           \
   do {                                          \
     if ((expr) != hipSuccess) return NS_ERR_HIP; \
@@ -771,6 +785,12 @@ int ns_batch_max_link_packets(const ns_batch_matrices_t *win, const uint64_t *of
   return NS_OK;
 }
 
+int ns_accumulate_workspace_size(uint64_t na, uint64_t nb, uint64_t *bytes) {
+  if (!bytes) return NS_ERR_INVALID_ARG;
+  *bytes = merge_plan(na + nb).total;
+  return NS_OK;
+}
+
 int ns_accumulate(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
                   ns_matrix_t *acc_out, void *ws, uint64_t ws_bytes, void *stream) {
   if (!acc_in || !win || !acc_out) return NS_ERR_INVALID_ARG;
@@ -788,13 +808,14 @@ int ns_accumulate(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
   if (sign < 0 && win->packets > acc_in->packets) return NS_ERR_UNDERFLOW;
   const uint64_t need = sign > 0 ? na + nb : na;
   if (acc_out->capacity < need) return NS_ERR_CAPACITY;
-  Ws w;
-  int rc = check_ws(ws, ws_bytes, na + nb, 1, &w);
-  if (rc) return rc;
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % kAlign) return NS_ERR_WORKSPACE;
+  const MergeLayout ML = merge_plan(na + nb);
+  if (ws_bytes < ML.total) return NS_ERR_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const uint64_t tiles = (na + nb) / kMergeTile + 2;
-  uint64_t *lbs = w.at<uint64_t>(w.L.lbs);
-  HIP_TRY(launch_fill32(w.at<uint32_t>(w.L.tickets), kMaxTickets, 0, s));
+  const uint64_t tiles = ML.tiles;
+  uint32_t *ticket = static_cast<uint32_t *>(ws);
+  uint64_t *lbs = reinterpret_cast<uint64_t *>(static_cast<uint8_t *>(ws) + ML.lbs);
+  HIP_TRY(launch_fill32(ticket, 1, 0, s));
   HIP_TRY(launch_fill64(lbs, tiles, 0, s));
   MergeArgs a{};
   a.ka = acc_in->keys;
@@ -811,7 +832,7 @@ int ns_accumulate(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
   a.nc_max = acc_out->capacity;
   a.sign = sign;
   a.lb = lbs;
-  a.ticket = w.ticket();
+  a.ticket = ticket;
   HIP_TRY(timed(K_MERGE, s, [&] { return launch_merge(a, tiles, s); }));
   acc_out->packets = sign > 0 ? acc_in->packets + win->packets : acc_in->packets - win->packets;
   return NS_OK;

@@ -62,7 +62,8 @@ class BatchMatricesView(ctypes.Structure):
                 ("nnz", ctypes.c_void_p), ("capacity", ctypes.c_uint64)]
 
 
-EXPORTS = ("ns_workspace_size", "ns_build_matrix", "ns_accumulate", "ns_stats",
+EXPORTS = ("ns_workspace_size", "ns_build_matrix", "ns_accumulate_workspace_size",
+           "ns_accumulate", "ns_stats",
            "ns_stream_workspace_size", "ns_build_matrix_streamed",
            "ns_stats_csr_workspace_size", "ns_stats_csr",
            "ns_batch_stats", "ns_batch_stats_eager", "ns_max_link_packets",
@@ -98,6 +99,7 @@ def load(path: str = LIB_PATH):
     lib.ns_build_matrix.argtypes = [P, P, U64, PM, P, U64, P]
     lib.ns_accumulate.argtypes = [PM, PM, I, PM, P, U64, P]
     lib.ns_stream_workspace_size.argtypes = [U64, U64, ctypes.POINTER(U64)]
+    lib.ns_accumulate_workspace_size.argtypes = [U64, U64, ctypes.POINTER(U64)]
     lib.ns_stats_csr_workspace_size.argtypes = [U64, ctypes.POINTER(U64)]
     lib.ns_stats_csr.argtypes = [P, P, U64, P, P, U64, U64, P, P, U64, P]
     lib.ns_build_matrix_streamed.argtypes = [P, P, U64, U64, PM, P, U64, P, P]
@@ -274,8 +276,30 @@ def build_matrix_streamed(src, dst, out: Matrix, ws: StreamWorkspace, stream=Non
     return out
 
 
-def accumulate(acc_in: Matrix, win: Matrix, sign: int, acc_out: Matrix, ws: Workspace,
-               stream=None) -> Matrix:
+def accumulate_workspace_size(na: int, nb: int) -> int:
+    out = ctypes.c_uint64()
+    _check(load().ns_accumulate_workspace_size(int(na), int(nb), ctypes.byref(out)),
+           "ns_accumulate_workspace_size")
+    return int(out.value)
+
+
+class MergeWorkspace:
+    """Device scratch memory of ns_accumulate for inputs of at most `na` and
+    `nb` entries (far smaller than a Workspace, which also serves)."""
+
+    def __init__(self, na: int, nb: int, device="cuda"):
+        torch = _torch()
+        self.nbytes = accumulate_workspace_size(na, nb)
+        self.buf = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
+        assert self.buf.data_ptr() % 256 == 0
+
+    @property
+    def ptr(self):
+        return ctypes.c_void_p(self.buf.data_ptr())
+
+
+def accumulate(acc_in: Matrix, win: Matrix, sign: int, acc_out: Matrix,
+               ws: "Workspace | MergeWorkspace", stream=None) -> Matrix:
     """ns_accumulate: acc_out = acc_in + sign * win (union-add / subtract)."""
     a, b, c = acc_in.view(), win.view(), acc_out.view()
     _check(load().ns_accumulate(ctypes.byref(a), ctypes.byref(b), int(sign), ctypes.byref(c),

@@ -75,6 +75,20 @@ def test_host_argument_errors(lib):
     small = ns.MatrixView(7168, 8192, 9216, 149, 0)
     assert lib.ns_accumulate(ctypes.byref(a), ctypes.byref(b), 1, ctypes.byref(small), ws, 1 << 40, None) == -2
     assert lib.ns_accumulate(ctypes.byref(b), ctypes.byref(a), -1, ctypes.byref(c), ws, 1 << 40, None) == -5
+    # accumulate workspace: the merge needs a ticket and one word per merge tile
+    need = ctypes.c_uint64()
+    assert lib.ns_accumulate_workspace_size(100, 50, None) == -1
+    assert lib.ns_accumulate_workspace_size(100, 50, ctypes.byref(need)) == 0
+    assert 0 < need.value <= 4096
+    big = ctypes.c_uint64()
+    assert lib.ns_accumulate_workspace_size(1 << 31, 1 << 31, ctypes.byref(big)) == 0
+    assert big.value >= 8 * ((1 << 32) // (256 * 8)) and big.value < (1 << 32) // 64
+    full = ctypes.c_uint64()
+    assert lib.ns_workspace_size(150, 1, ctypes.byref(full)) == 0 and full.value >= need.value
+    assert lib.ns_accumulate(ctypes.byref(a), ctypes.byref(b), 1, ctypes.byref(c), ws,
+                             need.value - 1, None) == -3
+    assert lib.ns_accumulate(ctypes.byref(a), ctypes.byref(b), 1, ctypes.byref(c),
+                             ctypes.c_void_p((1 << 20) + 8), 1 << 40, None) == -3
     # stats of a matrix holding 2^32 packets or more is out of range
     huge = ns.MatrixView(1024, 2048, 3072, 100, 1 << 32)
     assert lib.ns_stats(ctypes.byref(huge), ctypes.c_void_p(256), ws, 1 << 40, None) == -6

@@ -228,11 +228,11 @@ def test_union_add_past_2p31_entries():
                        torch.tensor([nb], dtype=torch.int64, device=dev), nb, nb)
     torch.cuda.empty_cache()
     N = half + nb
-    ws = ns.Workspace(N, 1, device=dev)
     C = ns.Matrix(N, device=dev)
     st = torch.zeros(8, dtype=torch.int64, device=dev)
-    say("ns_accumulate A + B, then ns_stats")
-    ns.accumulate(A, B, 1, C, ws)
+    say("ns_accumulate A + B (merge workspace), then ns_stats")
+    ns.accumulate(A, B, 1, C, ns.MergeWorkspace(half, nb, device=dev))
+    ws = ns.Workspace(N, 1, device=dev)
     ns.stats(C, st, ws)
     torch.cuda.synchronize()
     assert ns.device_status() == 0

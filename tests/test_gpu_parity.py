@@ -319,6 +319,34 @@ def test_accumulate_add_subtract(gpu):
     assert ns.stats_numpy(out).tolist() == [0] * 8
 
 
+def test_accumulate_with_its_own_small_workspace(gpu):
+    """ns_accumulate with a workspace of exactly ns_accumulate_workspace_size
+    bytes (one ticket and the merge tiles' look-back words): a sum and a
+    difference in a row on the one workspace, against the oracle."""
+    torch, ns = gpu
+    say("accumulate, merge workspace")
+    s1, d1 = zipf_packets(21, 70_000, pool=900)
+    s2, d2 = zipf_packets(22, 45_000, pool=900)
+    ws = ns.Workspace(70_000, 1)
+    A, B = ns.Matrix(70_000), ns.Matrix(45_000)
+    ns.build_matrix(up32(torch, s1), up32(torch, d1), A, ws)
+    ns.build_matrix(up32(torch, s2), up32(torch, d2), B, ws)
+    mw = ns.MergeWorkspace(115_000, 45_000)  # the larger of the two calls' bounds
+    assert mw.nbytes < 4096 < ws.nbytes
+    C, D = ns.Matrix(115_000), ns.Matrix(115_000)
+    ns.accumulate(A, B, 1, C, mw)
+    ns.accumulate(C, B, -1, D, mw)
+    torch.cuda.synchronize()
+    assert ns.device_status() == 0
+    ka, ca = oracle.build_matrix(s1, d1)
+    kb, cb = oracle.build_matrix(s2, d2)
+    kc, cc = oracle.accumulate(ka, ca, kb, cb, 1)
+    for M, (wk, wc) in [(C, (kc, cc)), (D, (ka, ca))]:
+        k, c = M.numpy()
+        assert np.array_equal(k, wk) and np.array_equal(c, wc)
+    assert C.packets == 115_000 and D.packets == 70_000
+
+
 def test_accumulate_edge_cases(gpu):
     torch, ns = gpu
     say("accumulate edges")
