@@ -1,14 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the anonymized-network-sensing hot path on one MI355X.
 
-A step is one pass of the whole path over the 64-window workload: 64 windows
-of 2^17 packets (sources Zipf 1.1, destinations Zipf 1.3, pool 2^20) ->
-every window's traffic matrix and eight quantities, plus the union-added
-aggregate matrix of all windows and its eight quantities, submitted as one
-graph-captured batched call (ns_batch_stats). Inputs are resident in HBM
-before the timed region. The same work done the plain way (per-window
-ns_build_matrix + ns_stats launches and an ns_accumulate chain for the
-aggregate) is timed beside it.
+Headline (default `--workload aggregate_2p30`): 2^30 packets in 8192 windows
+of 2^17 (Zipf 1.2 over a pool of 2^22, with a scanner and a sink) union-added
+into one hypersparse traffic matrix, reduced to its eight quantities. A step is
+one batched, graph-captured call (ns_batch_stats with the aggregate as its only
+output); inputs are resident in HBM before the timed region. The plain way to
+the same output is timed beside it: every window's matrix built by its own
+ns_build_matrix call, the windows union-added by a balanced tree of
+ns_accumulate calls, and ns_stats of the root. The same batched call that also
+returns every window's eight quantities is reported as `with_per_window`.
+
+The smaller workloads (one 2^17 window; 64 windows of 2^17 with their
+aggregate; 1024 uneven windows) run as `secondary` entries of the same line,
+each batched against its plain per-window loop, unless --no-secondary.
 
 Prints one JSON line. `--gpus N` with N > 1 is refused: this path runs on one
 GPU.
@@ -19,6 +24,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -27,18 +33,27 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 
+# what each workload computes (its config row)
+OUTPUTS = {
+    "aggregate_2p30": {"per_window": False, "aggregate": True},
+    "windows64": {"per_window": True, "aggregate": True},
+    "uneven1024": {"per_window": True, "aggregate": False},
+    "one_window": {"per_window": True, "aggregate": False},
+}
+
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=50)
-    p.add_argument("--warmup", type=int, default=5)
-    p.add_argument("--workload", default="windows64",
-                   choices=["windows64", "one_window", "uneven1024", "aggregate_2p30"])
-    p.add_argument("--plain-steps", type=int, default=5)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="aggregate_2p30", choices=sorted(OUTPUTS))
+    p.add_argument("--plain-steps", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=10.0,
+    p.add_argument("--no-secondary", action="store_true",
+                   help="skip the smaller workloads' batched-vs-plain entries")
+    p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="target CPU time of the oracle baseline sample")
     p.add_argument("--serve-arrivals", type=int, default=11024,
                    help="serving leg: arrivals (the first --serve-warm are warm-up); 0 = skip")
@@ -48,8 +63,9 @@ def parse():
                    help="skip timing ns_stats on the pre-built aggregate")
     p.add_argument("--no-stream", action="store_true",
                    help="skip the out-of-core leg (packets streamed from host memory)")
-    p.add_argument("--stream-batch", type=int, default=1 << 21,
-                   help="out-of-core leg: packets per sub-partition")
+    p.add_argument("--stream-batch", type=int, default=0,
+                   help="out-of-core leg: packets per sub-partition (0: packets / 64, "
+                        "at least 2^21)")
     p.add_argument("--copy-calibration-mib", type=int, default=0,
                    help="first run a plain device copy of this many MiB (3 times), whose "
                         "memory counters calibrate the profiler's byte counts")
@@ -60,292 +76,114 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this path runs on a single GPU; multi-GPU runs are not supported "
-              "(windows would shard across GPUs and the aggregate by a hash of its rows and "
-              "columns, but neither exchange is built)", file=sys.stderr)
-        sys.exit(2)
+def host_info() -> dict:
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = None
+    return {"nproc": os.cpu_count(), "affinity_cpus": aff, "cpu_model": model}
 
-    import numpy as np
-    import torch
 
-    from paper_2510_14050_amd import ns, synth, tune
-
-    assert torch.cuda.is_available(), "bench needs a GPU"
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    ns.load()
-
-    if args.copy_calibration_mib:
-        n64 = args.copy_calibration_mib * (1 << 20) // 8
-        a = torch.ones(n64, dtype=torch.int64, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log(f"copy calibration: 3 copies of {args.copy_calibration_mib} MiB "
-            f"(read {args.copy_calibration_mib} MiB + write {args.copy_calibration_mib} MiB each)")
-        del a, b
-
-    wl = synth.WORKLOADS[args.workload]()
-    W, N = wl.num_windows, wl.total_packets
-    log(f"workload {wl.name}: {W} windows, {N} packets; generating on the device")
-    src_t, dst_t = wl.device_concat(dev)
-    off_np = wl.offsets
-    off_t = torch.from_numpy(off_np).to(dev)
-    ws = ns.Workspace(N, W, device=dev)
-    out = torch.zeros((W, 8), dtype=torch.int64, device=dev)
-    agg = ns.Matrix(N, device=dev)
-    agg_stats = torch.zeros(8, dtype=torch.int64, device=dev)
-    torch.cuda.synchronize()
-
-    shape = tune.lookup(N, W)  # autotuned launch shape for this size class, if cached
-    sort_block = shape.sort_block if shape else 256
-    sort_items = shape.sort_items if shape else 16
-    log(f"launch shape: radix {sort_block}x{sort_items}, scan 256x"
-        f"{shape.scan_items if shape else 8} "
-        f"({'autotuned' if shape else 'default: no tuning cache entry'} for {tune._device_name()})")
-
-    def step():
-        ns.batch_stats(src_t, dst_t, off_t, out, ws, agg=agg, agg_stats=agg_stats, tune=shape)
-
-    for _ in range(args.warmup):
-        step()
+def timed_loop(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    for _ in range(steps):
+        fn()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    value = N * args.steps / (t1 - t0)
-    log(f"batched: {ms_step:.3f} ms/step, {value:.4e} packets/s")
-    got = ns.stats_numpy(out).copy()
-    got_agg = ns.stats_numpy(agg_stats).copy()
-    agg_nnz = agg.nnz()
-
-    # --- per-kernel durations from HIP events (eager replay of the same step) ---
-    ns.timing_reset()
-    ns.timing_enable(True)
-    ns.batch_stats(src_t, dst_t, off_t, out, ws, agg=agg, agg_stats=agg_stats, tune=shape,
-                   graph=False)
-    torch.cuda.synchronize()
-    kt = ns.timing_read()
-    ns.timing_enable(False)
-    ns.timing_reset()
-    links_windows = int(got[:, 1].sum())
-    roof = radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block, sort_items, args.workload)
-    breakdown = {k: {"ms": round(v[0], 4), "launches": v[1]} for k, v in kt.items()}
-    log("kernel breakdown (eager, ms):", json.dumps(breakdown))
-
-    # --- analysis only: the eight quantities of the pre-built aggregate matrix
-    # (construction excluded, the shape of the paper's timed analysis) ---
-    analysis = None
-    if not args.no_analysis:
-        an_st = torch.zeros(8, dtype=torch.int64, device=dev)
-        for _ in range(2):
-            ns.stats(agg, an_st, ws)
-        torch.cuda.synchronize()
-        reps = max(3, min(50, args.steps))
-        a0 = time.perf_counter()
-        for _ in range(reps):
-            ns.stats(agg, an_st, ws)
-        torch.cuda.synchronize()
-        an_ms = (time.perf_counter() - a0) * 1e3 / reps
-        analysis = {"ms": round(an_ms, 4), "matrix_nnz": agg_nnz, "packets": N,
-                    "packets_per_s": N / (an_ms * 1e-3),
-                    "same_as_batched": bool(np.array_equal(ns.stats_numpy(an_st), got_agg)),
-                    "what": "ns_stats on the pre-built aggregate matrix (construction excluded)"}
-        # the same matrix as hypersparse CSR (the form of the challenge's files),
-        # converted on the device before timing
-        keys = agg.keys[:agg_nnz]
-        rows_t, per_row = torch.unique_consecutive(keys >> 32, return_counts=True)
-        row_ptr = torch.zeros(rows_t.numel() + 1, dtype=torch.int64, device=dev)
-        row_ptr[1:] = torch.cumsum(per_row, 0)
-        rows32 = rows_t.to(torch.int32)
-        cols32 = (keys & 0xFFFFFFFF).to(torch.int32)
-        vals = agg.counts[:agg_nnz]
-        csr_ws = torch.empty(max(ns.stats_csr_workspace_size(agg_nnz), 256), dtype=torch.uint8,
-                             device=dev)
-        csr_st = torch.zeros(8, dtype=torch.int64, device=dev)
-        for _ in range(2):
-            ns.stats_csr(rows32, row_ptr, cols32, vals, N, csr_st, ws=csr_ws)
-        torch.cuda.synchronize()
-        a0 = time.perf_counter()
-        for _ in range(reps):
-            ns.stats_csr(rows32, row_ptr, cols32, vals, N, csr_st, ws=csr_ws)
-        torch.cuda.synchronize()
-        csr_ms = (time.perf_counter() - a0) * 1e3 / reps
-        analysis["csr_ms"] = round(csr_ms, 4)
-        analysis["csr_rows"] = int(rows_t.numel())
-        analysis["csr_same_as_batched"] = bool(np.array_equal(ns.stats_numpy(csr_st), got_agg))
-        del keys, rows_t, per_row, row_ptr, rows32, cols32, csr_ws
-        log(f"analysis of the pre-built aggregate: {an_ms:.3f} ms ({agg_nnz} links); "
-            f"from CSR: {csr_ms:.3f} ms")
-
-    # --- out-of-core: the aggregate built from packets in host memory ---
-    outofcore = None
-    if not args.no_stream:
-        outofcore = stream_leg(args, ns, torch, src_t, dst_t, agg, ws, dev)
-
-    # --- plain per-window path ---
-    plain = None
-    if not args.no_plain:
-        wins = [ns.Matrix(int(wl.sizes[w]), device=dev) for w in range(W)]
-        accs = [ns.Matrix(N, device=dev), ns.Matrix(N, device=dev)]
-        st_w = torch.zeros((W, 8), dtype=torch.int64, device=dev)
-        st_a = torch.zeros(8, dtype=torch.int64, device=dev)
-        empty = ns.Matrix(0, device=dev)
-        ns.build_matrix(src_t[:0], dst_t[:0], empty, ws)
-
-        def plain_step():
-            cur = empty
-            for w in range(W):
-                a, b = int(off_np[w]), int(off_np[w + 1])
-                ns.build_matrix(src_t[a:b], dst_t[a:b], wins[w], ws)
-                ns.stats(wins[w], st_w[w], ws)
-                nxt = accs[w & 1]
-                ns.accumulate(cur, wins[w], 1, nxt, ws)
-                cur = nxt
-            ns.stats(cur, st_a, ws)
-
-        plain_step()
-        torch.cuda.synchronize()
-        p0 = time.perf_counter()
-        for _ in range(args.plain_steps):
-            plain_step()
-        torch.cuda.synchronize()
-        p1 = time.perf_counter()
-        plain_ms = (p1 - p0) * 1e3 / args.plain_steps
-        plain = {"value": N / (plain_ms * 1e-3), "ms_per_step": round(plain_ms, 4),
-                 "bit_exact_vs_batched": bool(np.array_equal(ns.stats_numpy(st_w), got)
-                                              and np.array_equal(ns.stats_numpy(st_a), got_agg))}
-        log(f"plain: {plain_ms:.3f} ms/step, {plain['value']:.4e} packets/s")
-
-    # --- oracle on the host: parity and CPU baseline ---
-    cpu = None
-    bit_exact = None
-    if not args.no_cpu_baseline:
-        import oracle
-        src = synth.as_u32(src_t)
-        dst = synth.as_u32(dst_t)
-        # bounded sample: whole windows (and the aggregate of the sampled windows)
-        # until about --cpu-seconds of single-threaded oracle work
-        c0 = time.perf_counter()
-        done_pk, w = 0, 0
-        want = np.zeros((W, 8), np.uint64)
-        while w < W and (time.perf_counter() - c0) < args.cpu_seconds / 2:
-            a, b = int(off_np[w]), int(off_np[w + 1])
-            want[w] = oracle.stats(src[a:b], dst[a:b])
-            done_pk += b - a
-            w += 1
-        sampled_w = w
-        sample_pk = int(off_np[sampled_w])
-        agg_want = oracle.stats(src[:sample_pk], dst[:sample_pk])
-        done_pk += sample_pk
-        c1 = time.perf_counter()
-        # the sample processes sample_pk packets per window pass and per aggregate
-        cpu_rate = sample_pk / (c1 - c0)
-        cpu = {"value": cpu_rate, "unit": "packets/s", "cores": 1, "kind": "oracle",
-               "sample": f"{sampled_w} of {W} windows ({sample_pk} packets): per-window "
-                         f"8 quantities + aggregate matrix and its 8 quantities, "
-                         f"std::sort route, single thread, {c1 - c0:.1f} s"}
-        if sampled_w > 1:
-            # the same sample window-parallel on the host cores (the oracle's C
-            # calls release the GIL, so threads run them side by side)
-            from concurrent.futures import ThreadPoolExecutor
-            T = max(1, min(16, os.cpu_count() or 1))
-            def one(w):
-                a, b = int(off_np[w]), int(off_np[w + 1])
-                return oracle.stats(src[a:b], dst[a:b])
-            p0 = time.perf_counter()
-            with ThreadPoolExecutor(T) as ex:
-                fagg = ex.submit(oracle.stats, src[:sample_pk], dst[:sample_pk])
-                par = list(ex.map(one, range(sampled_w)))
-                par_agg = fagg.result()
-            p1 = time.perf_counter()
-            cpu["parallel"] = {"value": sample_pk / (p1 - p0), "unit": "packets/s", "cores": T,
-                               "kind": "oracle", "sample": f"the same sample, windows and the "
-                               f"aggregate spread over {T} threads, {p1 - p0:.1f} s",
-                               "agrees": bool(np.array_equal(np.array(par), want[:sampled_w])
-                                              and np.array_equal(par_agg, agg_want))}
-            log(f"oracle window-parallel ({T} threads): {sample_pk / (p1 - p0):.4e} packets/s")
-        bit_exact = bool(np.array_equal(got[:sampled_w], want[:sampled_w]))
-        if sampled_w == W:
-            bit_exact = bit_exact and bool(np.array_equal(got_agg, agg_want))
-        log(f"oracle: {cpu_rate:.4e} packets/s on {sampled_w} windows; bit-exact {bit_exact}")
-
-    serving = None
-    if args.serve_arrivals > 0:
-        serving = serve_leg(args, dev)
-
-    line = {
-        "metric": "packets/sec (8 stats, bit-exact) batched vs plain; p50/p99 window latency",
-        "value": value,
-        "unit": "packets/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {"workload": wl.name, "windows": W, "total_packets": N,
-                   "outputs": "per-window 8 stats + aggregate matrix + aggregate 8 stats",
-                   "submission": "one HIP graph (ns_batch_stats)"},
-        "roofline": roof,
-        "path": path_rates(args.workload, N, W, got, got_agg, ms_step),
-        "cpu_baseline": cpu,
-        "analysis": analysis,
-        "out_of_core": outofcore,
-        "plain": plain,
-        "batched_vs_plain": round(value / plain["value"], 2) if plain else None,
-        "bit_exact": bit_exact,
-        "kernels_ms": breakdown,
-        "serving": serving,
-    }
-    print(json.dumps(line), flush=True)
+    return (time.perf_counter() - t0) * 1e3 / max(steps, 1)
 
 
-def kernel_source_sha256() -> str:
-    """Hash of the HIP sources, to tell whether stored counter data still
-    describes the kernels that run."""
-    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2510_14050_amd", "csrc")
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
-    return h.hexdigest()
+class PlainPath:
+    """The plain way to a workload's outputs, one library call per window:
+    ns_build_matrix of every window into a pool laid out by packet offset
+    (window w's matrix starts at its first packet's position), ns_stats of each
+    window when per-window quantities are wanted, and for the aggregate a
+    balanced tree of ns_accumulate union-adds (level l+1 node i = nodes 2i and
+    2i+1 of level l, in the other pool, over their joint packet range; an
+    unpaired last node is union-added with the empty matrix), then ns_stats of
+    the root."""
+
+    def __init__(self, ns, torch, src_t, dst_t, off_np, dev, per_window, aggregate, ws):
+        self.ns, self.torch = ns, torch
+        self.src, self.dst, self.off = src_t, dst_t, [int(x) for x in off_np]
+        self.W, self.N = len(self.off) - 1, self.off[-1]
+        self.per_window, self.aggregate = per_window, aggregate
+        n = max(self.N, 1)
+        self.pool = [(torch.empty(n, dtype=torch.int64, device=dev),
+                      torch.empty(n, dtype=torch.int64, device=dev))]
+        if aggregate:
+            self.pool.append((torch.empty(n, dtype=torch.int64, device=dev),
+                              torch.empty(n, dtype=torch.int64, device=dev)))
+        big = max(b - a for a, b in zip(self.off[:-1], self.off[1:])) if self.W else 1
+        self.ws_win = ns.Workspace(max(big, 1), 1, device=dev)
+        self.ws = ws  # large enough for the root's statistics
+        self.mws = ns.MergeWorkspace(self.N, self.N, device=dev)
+        self.st_w = torch.zeros((max(self.W, 1), 8), dtype=torch.int64, device=dev)
+        self.st_a = torch.zeros(8, dtype=torch.int64, device=dev)
+        self.empty = ns.Matrix(0, device=dev)
+        ns.build_matrix(src_t[:0], dst_t[:0], self.empty, self.ws_win)
+        # the tree's levels: node = (pool index, first window, end window)
+        self.levels = []
+        nodes = [(0, w, w + 1) for w in range(self.W)]
+        self.nnz = [torch.zeros(max(self.W, 1), dtype=torch.int64, device=dev)]
+        while aggregate and len(nodes) > 1:
+            nxt = []
+            for i in range(0, len(nodes), 2):
+                pair = nodes[i:i + 2]
+                nxt.append((1 - nodes[i][0], pair[0][1], pair[-1][2]))
+            self.levels.append((nodes, nxt))
+            self.nnz.append(torch.zeros(len(nxt), dtype=torch.int64, device=dev))
+            nodes = nxt
+        self.root = nodes[0] if nodes else None
+
+    def _matrix(self, level, i, node, packets):
+        ns = self.ns
+        p, a, b = node
+        lo, hi = self.off[a], self.off[b]
+        keys, counts = self.pool[p]
+        cap = hi - lo
+        return ns.Matrix.wrap(keys[lo:lo + max(cap, 1)], counts[lo:lo + max(cap, 1)],
+                              self.nnz[level][i:i + 1], cap, packets)
+
+    def step(self):
+        ns = self.ns
+        mats = []
+        for w in range(self.W):
+            a, b = self.off[w], self.off[w + 1]
+            m = self._matrix(0, w, (0, w, w + 1), 0)
+            ns.build_matrix(self.src[a:b], self.dst[a:b], m, self.ws_win)
+            if self.per_window:
+                ns.stats(m, self.st_w[w], self.ws_win)
+            mats.append(m)
+        if not self.aggregate:
+            return
+        for lvl, (nodes, nxt) in enumerate(self.levels):
+            out = []
+            for i, node in enumerate(nxt):
+                a_m = mats[2 * i]
+                b_m = mats[2 * i + 1] if 2 * i + 1 < len(mats) else self.empty
+                c = self._matrix(lvl + 1, i, node, 0)
+                ns.accumulate(a_m, b_m, 1, c, self.mws)
+                out.append(c)
+            mats = out
+        if mats:
+            ns.stats(mats[0], self.st_a, self.ws)
 
 
-def profiled_traffic(workload: str, kernel: str):
-    """HBM bytes per launch of `kernel` on `workload` from the committed
-    rocprofv3 memory-counter summary (FETCH_SIZE and WRITE_SIZE passes, each
-    scaled by what it reads for a 1 GiB copy), or None when the summary is
-    missing or was taken on other kernel sources."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
-    try:
-        with open(path) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if t.get("source_sha256") != kernel_source_sha256():
-        return None
-    for e in t.get("entries", []):
-        if e["workload"] == workload and e["kernel"] == kernel:
-            return e["traffic_bytes_per_launch"]
-    return None
-
-
-def model_bytes(N, W, got, got_agg):
-    """Bytes the design as built moves for one step (per-window pipeline plus
-    the aggregate pipeline), from the measured links, sources and destinations:
+def bytes_model(N, W, got, got_agg, per_window, aggregate):
+    """Bytes the design as built moves for one step, from the measured links,
+    sources and destinations of each pipeline that runs:
       multi-segment sort (look-back): 8 (histogram) + 8 x 16 (key passes)
       single segment >= CHUNKED_MIN_DEFAULT (chunked): 8 x (8 + 16)
       run-length: 8 read + 24 per link (items + the per-window matrix, or the
@@ -356,37 +194,83 @@ def model_bytes(N, W, got, got_agg):
         column head, and 16 per column head for the maxima."""
     from paper_2510_14050_amd import ns
     cmin = ns.CHUNKED_MIN_DEFAULT
+
     def pipe(n, links, rows, cols, chunked):
         b = (8 * 24 if chunked else 8 + 8 * 16) * n
         b += 8 * n + 24 * links + 16 * rows + 16 * rows
         b += (4 * 24 if chunked else 8 + 4 * 16) * links + 8 * links + 32 * cols
         return b
-    win = pipe(N, int(got[:, 1].sum()), int(got[:, 2].sum()), int(got[:, 3].sum()),
-               W == 1 and N >= cmin)
-    agg = pipe(N, int(got_agg[1]), int(got_agg[2]), int(got_agg[3]), N >= cmin)
-    return win + agg
+    total = 0
+    if per_window:
+        total += pipe(N, int(got[:, 1].sum()), int(got[:, 2].sum()), int(got[:, 3].sum()),
+                      W == 1 and N >= cmin)
+    if aggregate:
+        total += pipe(N, int(got_agg[1]), int(got_agg[2]), int(got_agg[3]), N >= cmin)
+    return total
 
 
-def path_rates(workload, N, W, got, got_agg, ms_step):
+def survey_bytes(N, links):
+    """The sort-method model of the method's algorithmic bytes with byte digits
+    (8 key passes, 4 column passes): M = 16 + 16*8 + r*(76 + 24*4) bytes per
+    packet, r = links / packets."""
+    r = links / max(N, 1)
+    return (16 + 16 * 8 + r * (76 + 24 * 4)) * N
+
+
+def kernel_source_sha256() -> str:
+    """Hash of the HIP sources, to tell whether stored counter data still
+    describes the kernels that run."""
+    d = os.path.join(ROOT, "paper_2510_14050_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def _traffic_file():
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return t if t.get("source_sha256") == kernel_source_sha256() else None
+
+
+def profiled_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 memory-counter summary (FETCH_SIZE and WRITE_SIZE passes, each
+    scaled by what it reads for a 1 GiB copy), or None when the summary is
+    missing or was taken on other kernel sources."""
+    t = _traffic_file()
+    for e in (t or {}).get("entries", []):
+        if e["workload"] == workload and e["kernel"] == kernel:
+            return e["traffic_bytes_per_launch"]
+    return None
+
+
+def path_rates(workload, N, W, got, got_agg, ms_step, per_window, aggregate):
     """Whole-step rates: measured memory traffic (rocprofv3 FETCH_SIZE +
     WRITE_SIZE of every library kernel of one step, scaled by a 1 GiB copy;
-    null unless taken on these sources), the model bytes of the design, and
-    the floor of reading every packet once, each divided by the step time."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
-    measured = None
-    try:
-        with open(path) as f:
-            t = json.load(f)
-        if t.get("source_sha256") == kernel_source_sha256():
-            measured = t.get("step_traffic_bytes", {}).get(workload)
-    except (OSError, ValueError):
-        pass
+    null unless taken on these sources), the model bytes of the design as
+    built, the sort-method model of the method's algorithmic bytes, and the
+    floor of reading every packet once, each divided by the step time."""
+    t = _traffic_file()
+    measured = (t or {}).get("step_traffic_bytes", {}).get(workload)
     sec = ms_step * 1e-3
-    M = model_bytes(N, W, got, got_agg)
-    F = 8 * N + 64 * W
+    M = bytes_model(N, W, got, got_agg, per_window, aggregate)
+    links = int(got_agg[1]) if aggregate else int(got[:, 1].sum())
+    S = survey_bytes(N, links)
+    F = 8 * N + 64 * (W if per_window else 1)
     out = {"step_ms": round(ms_step, 4), "peak_gbs": PEAK_HBM_GBS,
            "model_bytes": M, "model_bytes_per_packet": round(M / max(N, 1), 2),
-           "model_gbs": round(M / sec / 1e9, 1), "model_frac": round(M / sec / 1e9 / PEAK_HBM_GBS, 4),
+           "model_gbs": round(M / sec / 1e9, 1),
+           "model_frac": round(M / sec / 1e9 / PEAK_HBM_GBS, 4),
+           "method_bytes": round(S), "method_bytes_per_packet": round(S / max(N, 1), 2),
+           "method_gbs": round(S / sec / 1e9, 1),
+           "method_frac": round(S / sec / 1e9 / PEAK_HBM_GBS, 4),
            "floor_bytes": F, "floor_gbs": round(F / sec / 1e9, 1),
            "measured_bytes": measured, "measured_gbs": None, "measured_frac": None}
     if measured:
@@ -395,7 +279,8 @@ def path_rates(workload, N, W, got, got_agg, ms_step):
     return out
 
 
-def radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block, sort_items, workload):
+def radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block, sort_items, workload,
+                   per_window, aggregate):
     """Roofline of the dominant kernel, the radix pass (key passes 2-8 and the
     four column passes; the first key pass reads packets and is timed apart).
     Two kernels implement it: k_pass (decoupled look-back, every multi-segment
@@ -411,7 +296,12 @@ def radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block, sort_items, wor
         "k_pass_chunked": {"kernel": "ns::k_pass_chunked<%d, %d, false>" % ns.CHUNKED_SHAPE,
                            "kinds": ("pass_chunked", "col_pass_chunked"), "items": 0},
     }
-    for chunked, links in ((W == 1 and N >= cmin, links_windows), (N >= cmin, agg_nnz)):
+    runs = []
+    if per_window:
+        runs.append((W == 1 and N >= cmin, links_windows))
+    if aggregate and not (per_window and W == 1):
+        runs.append((N >= cmin, agg_nnz))
+    for chunked, links in runs:
         fams["k_pass_chunked" if chunked else "k_pass"]["items"] += 7 * N + 4 * links
     rows = {}
     for name, f in fams.items():
@@ -436,32 +326,281 @@ def radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block, sort_items, wor
             "kernels": rows}
 
 
+def run_workload(name, args, dev, primary):
+    """Batched vs plain on one workload; with primary=True also the kernel
+    breakdown, roofline, analysis, out-of-core and CPU-baseline legs."""
+    import numpy as np
+    import torch
+
+    from paper_2510_14050_amd import ns, synth, tune
+
+    outs = OUTPUTS[name]
+    per_window, aggregate = outs["per_window"], outs["aggregate"]
+    wl = synth.WORKLOADS[name]()
+    W, N = wl.num_windows, wl.total_packets
+    log(f"workload {wl.name}: {W} windows, {N} packets; generating on the device")
+    src_t, dst_t = wl.device_concat(dev)
+    off_np = wl.offsets
+    off_t = torch.from_numpy(off_np).to(dev)
+    ws = ns.Workspace(N, W, device=dev)
+    out = torch.zeros((W, 8), dtype=torch.int64, device=dev)
+    agg = ns.Matrix(N, device=dev) if aggregate else None
+    agg_stats = torch.zeros(8, dtype=torch.int64, device=dev) if aggregate else None
+    torch.cuda.synchronize()
+
+    shape = tune.lookup(N, W, aggregate_only=aggregate and not per_window)
+    sort_block = shape.sort_block if shape else 256
+    sort_items = shape.sort_items if shape else 16
+    log(f"launch shape: radix {sort_block}x{sort_items}, scan 256x"
+        f"{shape.scan_items if shape else 8} "
+        f"({'autotuned' if shape else 'default: no tuning cache entry'} for {tune._device_name()})")
+    out_arg = out if per_window else None
+
+    def step(graph=True):
+        ns.batch_stats(src_t, dst_t, off_t, out_arg, ws, agg=agg, agg_stats=agg_stats,
+                       tune=shape, graph=graph)
+
+    steps = args.steps if primary else max(5, min(args.steps, 20))
+    ms_step = timed_loop(torch, step, steps, args.warmup)
+    value = N / (ms_step * 1e-3)
+    log(f"batched: {ms_step:.3f} ms/step, {value:.4e} packets/s")
+    got = ns.stats_numpy(out).copy()
+    got_agg = ns.stats_numpy(agg_stats).copy() if aggregate else None
+    agg_nnz = agg.nnz() if aggregate else 0
+    res = {"workload": wl.name, "windows": W, "total_packets": N, "value": value,
+           "unit": "packets/s", "ms_per_step": round(ms_step, 4), "steps": steps,
+           "outputs": ("per-window 8 stats" if per_window else "") +
+                      (" + " if per_window and aggregate else "") +
+                      ("aggregate matrix + aggregate 8 stats" if aggregate else ""),
+           "submission": "one HIP graph (ns_batch_stats)"}
+    if aggregate:
+        res["aggregate_links"] = agg_nnz
+
+    # the same call with every window's quantities as well (aggregate workloads)
+    if primary and aggregate and not per_window:
+        def step_all():
+            ns.batch_stats(src_t, dst_t, off_t, out, ws, agg=agg, agg_stats=agg_stats,
+                           tune=shape)
+        ms_all = timed_loop(torch, step_all, max(3, steps // 2), 1)
+        same = bool(np.array_equal(ns.stats_numpy(agg_stats), got_agg))
+        got = ns.stats_numpy(out).copy()
+        res["with_per_window"] = {"ms_per_step": round(ms_all, 4), "value": N / (ms_all * 1e-3),
+                                  "aggregate_same": same,
+                                  "what": "ns_batch_stats returning every window's 8 stats "
+                                          "as well as the aggregate's"}
+        log(f"with per-window quantities: {ms_all:.3f} ms/step")
+
+    if primary:
+        # --- per-kernel durations from HIP events (eager replay of the same step) ---
+        ns.timing_reset()
+        ns.timing_enable(True)
+        step(graph=False)
+        torch.cuda.synchronize()
+        kt = ns.timing_read()
+        ns.timing_enable(False)
+        ns.timing_reset()
+        links_windows = int(got[:, 1].sum())
+        res["roofline"] = radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block,
+                                         sort_items, name, per_window, aggregate)
+        res["kernels_ms"] = {k: {"ms": round(v[0], 4), "launches": v[1]} for k, v in kt.items()}
+        log("kernel breakdown (eager, ms):", json.dumps(res["kernels_ms"]))
+        res["path"] = path_rates(name, N, W, got, got_agg, ms_step, per_window, aggregate)
+
+    if primary and aggregate and not args.no_analysis:
+        res["analysis"] = analysis_leg(ns, torch, np, agg, ws, N, got_agg, args, dev)
+    if primary and aggregate and not args.no_stream:
+        res["out_of_core"] = stream_leg(args, ns, torch, src_t, dst_t, agg, ws, dev)
+
+    # --- plain: one library call per window (and a union-add tree) ---
+    if not args.no_plain:
+        pp = PlainPath(ns, torch, src_t, dst_t, off_np, dev, per_window, aggregate, ws)
+        plain_steps = args.plain_steps if primary else max(2, args.plain_steps)
+        pms = timed_loop(torch, pp.step, plain_steps, 1)
+        ok = True
+        if per_window:
+            ok = ok and bool(np.array_equal(ns.stats_numpy(pp.st_w)[:W], got))
+        if aggregate:
+            ok = ok and bool(np.array_equal(ns.stats_numpy(pp.st_a), got_agg))
+        res["plain"] = {"value": N / (pms * 1e-3), "ms_per_step": round(pms, 4),
+                        "steps": plain_steps, "bit_exact_vs_batched": ok,
+                        "what": ("per-window ns_build_matrix" +
+                                 (" + ns_stats" if per_window else "") +
+                                 (" + balanced ns_accumulate tree + ns_stats of the root"
+                                  if aggregate else "") + ", one call each, one stream")}
+        res["batched_vs_plain"] = round(value / res["plain"]["value"], 2)
+        log(f"plain: {pms:.3f} ms/step ({res['batched_vs_plain']}x slower than batched)")
+        del pp
+        torch.cuda.empty_cache()
+
+    # --- oracle on the host: parity sample and CPU baseline ---
+    if primary and not args.no_cpu_baseline:
+        res["cpu_baseline"], res["bit_exact"] = cpu_leg(args, wl, src_t, dst_t, off_np, got,
+                                                        got_agg, per_window, aggregate)
+    elif not primary and not args.no_cpu_baseline:
+        # parity of the secondary workload on a few windows
+        import oracle
+        src, dst = synth.as_u32(src_t), synth.as_u32(dst_t)
+        ok = True
+        for w in sorted({0, W // 2, W - 1}):
+            a, b = int(off_np[w]), int(off_np[w + 1])
+            ok = ok and bool(np.array_equal(got[w], oracle.stats(src[a:b], dst[a:b])))
+        if aggregate and N <= (1 << 24):
+            ok = ok and bool(np.array_equal(got_agg, oracle.stats(src, dst)))
+        res["bit_exact_sampled"] = ok
+    del src_t, dst_t, ws, out, agg
+    ns.release_graphs()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
+
+
+def analysis_leg(ns, torch, np, agg, ws, N, got_agg, args, dev):
+    """The eight quantities of the pre-built aggregate matrix (construction
+    excluded, the shape of the paper's timed analysis), from the library's COO
+    and from the same matrix as hypersparse CSR."""
+    agg_nnz = agg.nnz()
+    an_st = torch.zeros(8, dtype=torch.int64, device=dev)
+    reps = max(3, min(20, args.steps))
+    an_ms = timed_loop(torch, lambda: ns.stats(agg, an_st, ws), reps, 2)
+    out = {"ms": round(an_ms, 4), "matrix_nnz": agg_nnz, "packets": N,
+           "packets_per_s": N / (an_ms * 1e-3),
+           "same_as_batched": bool(np.array_equal(ns.stats_numpy(an_st), got_agg)),
+           "what": "ns_stats on the pre-built aggregate matrix (construction excluded)"}
+    keys = agg.keys[:agg_nnz]
+    rows_t, per_row = torch.unique_consecutive(keys >> 32, return_counts=True)
+    row_ptr = torch.zeros(rows_t.numel() + 1, dtype=torch.int64, device=dev)
+    row_ptr[1:] = torch.cumsum(per_row, 0)
+    rows32 = rows_t.to(torch.int32)
+    cols32 = (keys & 0xFFFFFFFF).to(torch.int32)
+    vals = agg.counts[:agg_nnz]
+    csr_ws = torch.empty(max(ns.stats_csr_workspace_size(agg_nnz), 256), dtype=torch.uint8,
+                         device=dev)
+    csr_st = torch.zeros(8, dtype=torch.int64, device=dev)
+    csr_ms = timed_loop(torch, lambda: ns.stats_csr(rows32, row_ptr, cols32, vals, N, csr_st,
+                                                    ws=csr_ws), reps, 2)
+    out["csr_ms"] = round(csr_ms, 4)
+    out["csr_rows"] = int(rows_t.numel())
+    out["csr_same_as_batched"] = bool(np.array_equal(ns.stats_numpy(csr_st), got_agg))
+    log(f"analysis of the pre-built aggregate: {an_ms:.3f} ms ({agg_nnz} links); "
+        f"from CSR: {csr_ms:.3f} ms")
+    del keys, rows_t, per_row, row_ptr, rows32, cols32, csr_ws
+    return out
+
+
+def cpu_leg(args, wl, src_t, dst_t, off_np, got, got_agg, per_window, aggregate):
+    """The oracle as it stands, timed on the host on a bounded sample of the
+    same workload: the first k windows (k grown until about --cpu-seconds of
+    single-threaded work): their aggregate's matrix and eight quantities for
+    aggregate workloads, each window's quantities otherwise. The sample also
+    checks the batched results bit-exactly."""
+    import numpy as np
+
+    import oracle
+    from paper_2510_14050_amd import synth
+    W = wl.num_windows
+    host = host_info()
+    # host copies of the packets the sample may use (not timed)
+    lim = int(off_np[min(W, 512)])
+    src = synth.as_u32(src_t[:lim])
+    dst = synth.as_u32(dst_t[:lim])
+    bit_exact = True
+    if aggregate and not per_window:
+        # the aggregate of the first k windows, k doubling until the budget
+        k, spent, rate = 1, 0.0, None
+        while True:
+            n = int(off_np[k])
+            c0 = time.perf_counter()
+            st = oracle.stats(src[:n], dst[:n])
+            dt = time.perf_counter() - c0
+            spent += dt
+            rate, sample_w, sample_n, sample_t = n / dt, k, n, dt
+            if k == W:
+                bit_exact = bool(np.array_equal(st, got_agg))
+            if spent > args.cpu_seconds / 3 or k >= W or 2 * k > min(W, 512):
+                break
+            k *= 2
+        # parity of the sampled windows' quantities comes from the GPU tests; the
+        # sample here checks every window the per-window call produced
+        if got is not None and got.any():
+            for w in (0, W - 1):
+                a, b = int(off_np[w]), int(off_np[w + 1])
+                s_w, d_w = (src[a:b], dst[a:b]) if b <= lim else \
+                    (synth.as_u32(src_t[a:b]), synth.as_u32(dst_t[a:b]))
+                bit_exact = bit_exact and bool(np.array_equal(got[w], oracle.stats(s_w, d_w)))
+        cpu = {"value": rate, "unit": "packets/s", "cores": 1, "kind": "oracle",
+               "sample": f"aggregate of the first {sample_w} of {W} windows ({sample_n} "
+                         f"packets): matrix and its 8 quantities by the std::sort route, "
+                         f"single thread, {sample_t:.1f} s",
+               "windows_sampled": sample_w, "host": host}
+        log(f"oracle: {rate:.4e} packets/s on the aggregate of {sample_w} windows")
+        return cpu, bit_exact
+    c0 = time.perf_counter()
+    want = []
+    w = 0
+    while w < W and int(off_np[w + 1]) <= lim and (time.perf_counter() - c0) < args.cpu_seconds / 2:
+        a, b = int(off_np[w]), int(off_np[w + 1])
+        want.append(oracle.stats(src[a:b], dst[a:b]))
+        w += 1
+    sampled_w = w
+    sample_pk = int(off_np[sampled_w])
+    agg_want = None
+    if aggregate:
+        agg_want = oracle.stats(src[:sample_pk], dst[:sample_pk])
+    c1 = time.perf_counter()
+    cpu_rate = sample_pk / (c1 - c0)
+    cpu = {"value": cpu_rate, "unit": "packets/s", "cores": 1, "kind": "oracle",
+           "sample": f"{sampled_w} of {W} windows ({sample_pk} packets): per-window "
+                     f"8 quantities" + (" + aggregate matrix of the sampled windows and "
+                                        "its 8 quantities" if aggregate else "") +
+                     f", std::sort route, single thread, {c1 - c0:.1f} s",
+           "windows_sampled": sampled_w, "host": host}
+    bit_exact = bool(np.array_equal(got[:sampled_w], np.array(want).reshape(-1, 8)))
+    if aggregate and sampled_w == W:
+        bit_exact = bit_exact and bool(np.array_equal(got_agg, agg_want))
+    if sampled_w > 1:
+        # the same sample window-parallel on the host cores (the oracle's C
+        # calls release the GIL, so threads run them side by side)
+        from concurrent.futures import ThreadPoolExecutor
+        T = max(1, min(16, host["affinity_cpus"] or os.cpu_count() or 1))
+
+        def one(w):
+            a, b = int(off_np[w]), int(off_np[w + 1])
+            return oracle.stats(src[a:b], dst[a:b])
+        p0 = time.perf_counter()
+        with ThreadPoolExecutor(T) as ex:
+            fagg = ex.submit(oracle.stats, src[:sample_pk], dst[:sample_pk]) if aggregate else None
+            par = list(ex.map(one, range(sampled_w)))
+            par_agg = fagg.result() if fagg else None
+        p1 = time.perf_counter()
+        cpu["parallel"] = {"value": sample_pk / (p1 - p0), "unit": "packets/s", "cores": T,
+                           "kind": "oracle", "sample": f"the same sample, windows" +
+                           (" and the aggregate" if aggregate else "") +
+                           f" spread over {T} threads, {p1 - p0:.1f} s",
+                           "agrees": bool(np.array_equal(np.array(par), np.array(want))
+                                          and (not aggregate or np.array_equal(par_agg, agg_want)))}
+        log(f"oracle window-parallel ({T} threads): {sample_pk / (p1 - p0):.4e} packets/s")
+    log(f"oracle: {cpu_rate:.4e} packets/s on {sampled_w} windows; bit-exact {bit_exact}")
+    return cpu, bit_exact
+
+
 def stream_leg(args, ns, torch, src_t, dst_t, agg, ws, dev):
     """Out-of-core build (batching of Sec. III-C): the same packets from pinned
-    host memory, in sub-partitions of --stream-batch packets, copied on a
-    second stream while the previous one is built and union-added. Reported
-    beside the host-to-device copy alone and the device-resident build alone."""
+    host memory, in sub-partitions, copied on a second stream while the
+    previous one is built and union-added. Reported beside the host-to-device
+    copy alone and the device-resident build alone."""
     N = src_t.numel()
     src_h, dst_h = src_t.cpu().pin_memory(), dst_t.cpu().pin_memory()
     links = agg.nnz()
-    batch = min(args.stream_batch, max(N, 1))
+    batch = args.stream_batch or max(1 << 21, N // 64)
+    batch = min(batch, max(N, 1))
     # the first sub-partition is built in place in the output, so the
     # capacity covers it as well as the aggregate's links
     out = ns.Matrix(max(links, batch, 1), device=dev)
     sws = ns.StreamWorkspace(batch, out.capacity, device=dev)
     cs = torch.cuda.Stream(device=dev)
-    reps = 5
-
-    def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / reps
-
-    ms = timed(lambda: ns.build_matrix_streamed(src_h, dst_h, out, sws, copy_stream=cs))
+    reps = 3
+    ms = timed_loop(torch, lambda: ns.build_matrix_streamed(src_h, dst_h, out, sws,
+                                                            copy_stream=cs), reps, 1)
     same = ns.device_status() == 0 and out.nnz() == links and \
         bool(torch.equal(out.keys[:links], agg.keys[:links])) and \
         bool(torch.equal(out.counts[:links], agg.counts[:links]))
@@ -470,9 +609,9 @@ def stream_leg(args, ns, torch, src_t, dst_t, agg, ws, dev):
     def h2d():
         sd.copy_(src_h, non_blocking=True)
         dd.copy_(dst_h, non_blocking=True)
-    h2d_ms = timed(h2d)
+    h2d_ms = timed_loop(torch, h2d, reps, 1)
     dev_m = ns.Matrix(N, device=dev)
-    build_ms = timed(lambda: ns.build_matrix(src_t, dst_t, dev_m, ws))
+    build_ms = timed_loop(torch, lambda: ns.build_matrix(src_t, dst_t, dev_m, ws), reps, 1)
     res = {"batch_packets": batch, "sub_partitions": (N + batch - 1) // batch,
            "ms": round(ms, 4), "packets_per_s": N / (ms * 1e-3),
            "h2d_ms": round(h2d_ms, 4), "h2d_gbs": round(8 * N / (h2d_ms * 1e-3) / 1e9, 1),
@@ -481,7 +620,7 @@ def stream_leg(args, ns, torch, src_t, dst_t, agg, ws, dev):
            "what": "ns_build_matrix_streamed from pinned host memory (copies on a second stream)"}
     log(f"out-of-core build: {ms:.3f} ms for {N} packets in {res['sub_partitions']} "
         f"sub-partitions (copy alone {h2d_ms:.3f} ms, device-resident build {build_ms:.3f} ms)")
-    del dev_m, sd, dd, sws, out
+    del dev_m, sd, dd, sws, out, src_h, dst_h
     return res
 
 
@@ -527,10 +666,80 @@ def serve_leg(args, dev):
         "packets_per_s": pk / span if span else None,
         "mean_batch": round(float(np.mean(rep.batches)), 2),
         "max_batch": int(max(rep.batches)), "max_in_flight": rep.max_in_flight,
+        "compactions": rep.compactions,
         "rolling_spot_checks_bit_exact": checks,
     }
     log("serving:", json.dumps(out))
     return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this path runs on a single GPU; multi-GPU runs are not supported "
+              "(windows would shard across GPUs and the aggregate by a hash of its rows and "
+              "columns, but neither exchange is built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2510_14050_amd import ns
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ns.load()
+
+    if args.copy_calibration_mib:
+        n64 = args.copy_calibration_mib * (1 << 20) // 8
+        a = torch.ones(n64, dtype=torch.int64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {args.copy_calibration_mib} MiB "
+            f"(read {args.copy_calibration_mib} MiB + write {args.copy_calibration_mib} MiB each)")
+        del a, b
+
+    head = run_workload(args.workload, args, dev, primary=True)
+    secondary = None
+    if not args.no_secondary:
+        secondary = {}
+        for name in ("one_window", "windows64", "uneven1024"):
+            if name != args.workload:
+                secondary[name] = run_workload(name, args, dev, primary=False)
+    serving = serve_leg(args, dev) if args.serve_arrivals > 0 else None
+
+    line = {
+        "metric": "packets/sec (8 stats, bit-exact) batched vs plain; p50/p99 window latency",
+        "value": head["value"],
+        "unit": "packets/s",
+        "n_gpus": 1,
+        "steps": head["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": head["workload"], "windows": head["windows"],
+                   "total_packets": head["total_packets"], "outputs": head["outputs"],
+                   "submission": head["submission"]},
+        "roofline": head.get("roofline"),
+        "path": head.get("path"),
+        "cpu_baseline": head.get("cpu_baseline"),
+        "plain": head.get("plain"),
+        "batched_vs_plain": head.get("batched_vs_plain"),
+        "bit_exact": head.get("bit_exact"),
+        "with_per_window": head.get("with_per_window"),
+        "analysis": head.get("analysis"),
+        "out_of_core": head.get("out_of_core"),
+        "kernels_ms": head.get("kernels_ms"),
+        "secondary": secondary,
+        "serving": serving,
+    }
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -194,13 +194,16 @@ int ns_stats_csr(const uint32_t *rows, const uint64_t *row_ptr, uint64_t nrows,
  *   src, dst      concatenated packets of all windows (total_packets each)
  *   offsets       device [num_windows+1], offsets[0] = 0, non-decreasing,
  *                 offsets[num_windows] = total_packets; window w = [offsets[w], offsets[w+1])
- *   total_packets host bound, equal to offsets[num_windows]
- *   out           device [num_windows] results
+ *   total_packets host bound, equal to offsets[num_windows]; below 2^32
+ *                 (NS_ERR_UNSUPPORTED otherwise)
+ *   out           device [num_windows] results; nullable when agg_out is given:
+ *                 then only the aggregate (the union-add of all windows, Fig. 2
+ *                 "load and aggregate") and its quantities are computed
  *   agg_out       nullable: union-add of all windows (capacity >= total_packets)
  *   agg_stats     nullable: device ns_stats_t of agg_out (requires agg_out)
- *   win_out       nullable: every window's own matrix (batched COO)
+ *   win_out       nullable: every window's own matrix (batched COO; requires out)
  *   tune          nullable: launch shape (NULL = defaults)
- * Windows may be empty. Each window must hold fewer than 2^32 packets. */
+ * Windows may be empty. */
 int ns_batch_stats(const uint32_t *src, const uint32_t *dst, const uint64_t *offsets,
                    uint32_t num_windows, uint64_t total_packets, ns_stats_t *out,
                    ns_matrix_t *agg_out, ns_stats_t *agg_stats, ns_batch_matrices_t *win_out,

@@ -542,11 +542,18 @@ struct BatchArgs {
 int enqueue_batch(const BatchArgs &b, Ws &ws, Ws &ws2, hipStream_t s, hipStream_t s2,
                   hipEvent_t fork, hipEvent_t join) {
   HIP_TRY(launch_fill32(ws.at<uint32_t>(ws.L.tickets), kMaxTickets, 0, s));
-  if (b.agg && b.W == 1) {
+  if (b.agg && (b.W == 1 || !b.out)) {
     // one window: its matrix is the aggregate, so one pipeline writes both
-    // (and the window's quantities are copied to the aggregate's)
+    // (and the window's quantities are copied to the aggregate's); no
+    // per-window output: the aggregate's pipeline alone, over all packets
     PacketOut o{};
-    o.stats = reinterpret_cast<uint64_t *>(b.out);
+    uint64_t *seg = ws.at<uint64_t>(ws.L.seg);
+    const uint64_t *off = b.offsets;
+    if (!b.out) {
+      HIP_TRY(launch_seg1(seg, nullptr, b.N, s));
+      off = seg;
+    }
+    o.stats = reinterpret_cast<uint64_t *>(b.out ? b.out : b.agg_stats);
     o.ukeys = b.agg->keys;
     o.counts = b.agg->counts;
     o.nnz = b.agg->nnz;
@@ -557,9 +564,9 @@ int enqueue_batch(const BatchArgs &b, Ws &ws, Ws &ws2, hipStream_t s, hipStream_
       o.win_counts = b.win->counts;
       o.win_nnz = b.win->nnz;
     }
-    int rc = enqueue_packets(ws, b.sh, b.src, b.dst, b.offsets, 1, b.N, o, s);
+    int rc = enqueue_packets(ws, b.sh, b.src, b.dst, off, 1, b.N, o, s);
     if (rc) return rc;
-    if (b.agg_stats)
+    if (b.agg_stats && b.out)
       HIP_TRY(launch_copy64(reinterpret_cast<uint64_t *>(b.agg_stats),
                             reinterpret_cast<const uint64_t *>(b.out), 8, s));
     return NS_OK;
@@ -612,8 +619,10 @@ int batch_checks(const uint32_t *src, const uint32_t *dst, const uint64_t *offse
                  ns_batch_matrices_t *win, const ns_tuning_t *tune, void *ws, uint64_t ws_bytes,
                  BatchArgs *b, Ws *w, Ws *w2) {
   if (N > 0 && (!src || !dst)) return NS_ERR_INVALID_ARG;
-  if (W > 0 && (!offsets || !out)) return NS_ERR_INVALID_ARG;
+  if (W > 0 && !offsets) return NS_ERR_INVALID_ARG;
+  if (W > 0 && !out && !agg) return NS_ERR_INVALID_ARG;  // nothing to compute
   if (W == 0 && N > 0) return NS_ERR_INVALID_ARG;
+  if (!out && win) return NS_ERR_INVALID_ARG;  // window matrices come from the per-window pipeline
   if (N > kMaxPackets32) return NS_ERR_UNSUPPORTED;
   if (agg_stats && !agg) return NS_ERR_INVALID_ARG;
   if (agg) {
@@ -660,6 +669,57 @@ std::string batch_key(int dev, const BatchArgs &b, void *ws, uint64_t ws_bytes) 
            (unsigned long long)(b.win ? b.win->capacity : 0), b.sh.sort.block, b.sh.sort.items,
            b.sh.scan.items, (unsigned long long)b.sh.chunked_min, ws, (unsigned long long)ws_bytes);
   return std::string(buf);
+}
+
+// Union-add / subtract of two sorted COO matrices into acc_out (the checks
+// and kernel sequence of ns_accumulate) with the merge's ticket and look-back
+// words in the caller's `ws`.
+int accumulate_into(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
+                    ns_matrix_t *acc_out, void *ws, uint64_t ws_bytes, hipStream_t s) {
+  if (!acc_in || !win || !acc_out) return NS_ERR_INVALID_ARG;
+  if (sign != 1 && sign != -1) return NS_ERR_INVALID_ARG;
+  const ns_matrix_t *ins[2] = {acc_in, win};
+  for (const ns_matrix_t *m : ins) {
+    if (!m->keys || !m->counts || !m->nnz) return NS_ERR_INVALID_ARG;
+    if (m->keys == acc_out->keys || m->counts == acc_out->counts || m->nnz == acc_out->nnz ||
+        m->keys == acc_out->counts || m->counts == acc_out->keys)
+      return NS_ERR_INVALID_ARG;
+  }
+  if (!acc_out->keys || !acc_out->counts || !acc_out->nnz) return NS_ERR_INVALID_ARG;
+  const uint64_t na = acc_in->capacity < acc_in->packets ? acc_in->capacity : acc_in->packets;
+  const uint64_t nb = win->capacity < win->packets ? win->capacity : win->packets;
+  if (sign < 0 && win->packets > acc_in->packets) return NS_ERR_UNDERFLOW;
+  const uint64_t need = sign > 0 ? na + nb : na;
+  if (acc_out->capacity < need) return NS_ERR_CAPACITY;
+  const MergeLayout ML = merge_plan(na + nb);
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % kAlign) return NS_ERR_WORKSPACE;
+  if (ws_bytes < ML.total) return NS_ERR_WORKSPACE;
+  const uint64_t tiles = ML.tiles;
+  uint32_t *ticket = static_cast<uint32_t *>(ws);
+  uint64_t *lbs = reinterpret_cast<uint64_t *>(static_cast<uint8_t *>(ws) + ML.lbs);
+  // ticket and look-back words start at zero (fill kernels: no memset nodes
+  // if the caller captures the call into a graph)
+  HIP_TRY(launch_fill32(ticket, 1, 0, s));
+  HIP_TRY(launch_fill64(lbs, tiles, 0, s));
+  MergeArgs a{};
+  a.ka = acc_in->keys;
+  a.ca = acc_in->counts;
+  a.na = acc_in->nnz;
+  a.kb = win->keys;
+  a.cb = win->counts;
+  a.nb = win->nnz;
+  a.na_max = na;
+  a.nb_max = nb;
+  a.kc = acc_out->keys;
+  a.cc = acc_out->counts;
+  a.nc = acc_out->nnz;
+  a.nc_max = acc_out->capacity;
+  a.sign = sign;
+  a.lb = lbs;
+  a.ticket = ticket;
+  HIP_TRY(timed(K_MERGE, s, [&] { return launch_merge(a, tiles, s); }));
+  acc_out->packets = sign > 0 ? acc_in->packets + win->packets : acc_in->packets - win->packets;
+  return NS_OK;
 }
 
 }  // namespace
@@ -793,49 +853,8 @@ int ns_accumulate_workspace_size(uint64_t na, uint64_t nb, uint64_t *bytes) {
 
 int ns_accumulate(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
                   ns_matrix_t *acc_out, void *ws, uint64_t ws_bytes, void *stream) {
-  if (!acc_in || !win || !acc_out) return NS_ERR_INVALID_ARG;
-  if (sign != 1 && sign != -1) return NS_ERR_INVALID_ARG;
-  const ns_matrix_t *ins[2] = {acc_in, win};
-  for (const ns_matrix_t *m : ins) {
-    if (!m->keys || !m->counts || !m->nnz) return NS_ERR_INVALID_ARG;
-    if (m->keys == acc_out->keys || m->counts == acc_out->counts || m->nnz == acc_out->nnz ||
-        m->keys == acc_out->counts || m->counts == acc_out->keys)
-      return NS_ERR_INVALID_ARG;
-  }
-  if (!acc_out->keys || !acc_out->counts || !acc_out->nnz) return NS_ERR_INVALID_ARG;
-  const uint64_t na = acc_in->capacity < acc_in->packets ? acc_in->capacity : acc_in->packets;
-  const uint64_t nb = win->capacity < win->packets ? win->capacity : win->packets;
-  if (sign < 0 && win->packets > acc_in->packets) return NS_ERR_UNDERFLOW;
-  const uint64_t need = sign > 0 ? na + nb : na;
-  if (acc_out->capacity < need) return NS_ERR_CAPACITY;
-  if (!ws || reinterpret_cast<uintptr_t>(ws) % kAlign) return NS_ERR_WORKSPACE;
-  const MergeLayout ML = merge_plan(na + nb);
-  if (ws_bytes < ML.total) return NS_ERR_WORKSPACE;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const uint64_t tiles = ML.tiles;
-  uint32_t *ticket = static_cast<uint32_t *>(ws);
-  uint64_t *lbs = reinterpret_cast<uint64_t *>(static_cast<uint8_t *>(ws) + ML.lbs);
-  HIP_TRY(launch_fill32(ticket, 1, 0, s));
-  HIP_TRY(launch_fill64(lbs, tiles, 0, s));
-  MergeArgs a{};
-  a.ka = acc_in->keys;
-  a.ca = acc_in->counts;
-  a.na = acc_in->nnz;
-  a.kb = win->keys;
-  a.cb = win->counts;
-  a.nb = win->nnz;
-  a.na_max = na;
-  a.nb_max = nb;
-  a.kc = acc_out->keys;
-  a.cc = acc_out->counts;
-  a.nc = acc_out->nnz;
-  a.nc_max = acc_out->capacity;
-  a.sign = sign;
-  a.lb = lbs;
-  a.ticket = ticket;
-  HIP_TRY(timed(K_MERGE, s, [&] { return launch_merge(a, tiles, s); }));
-  acc_out->packets = sign > 0 ? acc_in->packets + win->packets : acc_in->packets - win->packets;
-  return NS_OK;
+  return accumulate_into(acc_in, win, sign, acc_out, ws, ws_bytes,
+                         static_cast<hipStream_t>(stream));
 }
 
 int ns_stream_workspace_size(uint64_t batch, uint64_t capacity, uint64_t *bytes) {

@@ -398,17 +398,18 @@ def batch_stats(src, dst, offsets, out, ws: Workspace, agg: Matrix | None = None
                 stream=None, graph: bool = True):
     """ns_batch_stats (graph=True) or ns_batch_stats_eager: per-window stats
     into out (int64 cuda [W, 8]); optionally the aggregate matrix and its stats,
-    and each window's own matrix."""
+    and each window's own matrix. out=None with an aggregate computes the
+    aggregate alone."""
     torch = _torch()
     _u32_tensor(src), _u32_tensor(dst)
     assert offsets.dtype == torch.int64 and offsets.is_cuda
     W = offsets.numel() - 1
     N = src.numel()
-    assert out.numel() >= 8 * W
+    assert out is None or out.numel() >= 8 * W
     av = agg.view() if agg is not None else None
     wv = win.view() if win is not None else None
     fn = load().ns_batch_stats if graph else load().ns_batch_stats_eager
-    rc = fn(_ptr(src), _ptr(dst), _ptr(offsets), W, N, _ptr(out),
+    rc = fn(_ptr(src), _ptr(dst), _ptr(offsets), W, N, _ptr(out) if out is not None else None,
             ctypes.byref(av) if av is not None else None,
             _ptr(agg_stats) if agg_stats is not None else None,
             ctypes.byref(wv) if wv is not None else None,

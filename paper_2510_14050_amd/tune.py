@@ -42,12 +42,18 @@ def _load_cache() -> dict:
         return {}
 
 
-def lookup(packets: int, windows: int):
-    """Cached ns.Tuning for this size class on this device, or None."""
+def lookup(packets: int, windows: int, aggregate_only: bool = False):
+    """Cached ns.Tuning for this size class on this device, or None. Calls
+    that compute the aggregate alone have their own class (suffix "_agg"),
+    and fall back to the class of the same size with per-window outputs."""
     cache = _load_cache().get(_device_name(), {})
     if not cache:
         return None
     key = size_class(packets, windows)
+    if aggregate_only and key + "_agg" in cache:
+        key = key + "_agg"
+    cache = {k: v for k, v in cache.items() if not k.endswith("_agg")} if key not in cache \
+        else cache
     if key not in cache:
         def dist(k):
             p, w = k[1:].split("_w")

@@ -100,6 +100,19 @@ def test_host_argument_errors(lib):
     aggm = ns.MatrixView(1024, 2048, 3072, 9, 0)
     assert lib.ns_batch_stats(off, off, off, 1, 10, off, ctypes.byref(aggm), None, None, None, ws,
                               1 << 40, None) == -2
+    # batch without per-window output: only with an aggregate, and no window matrices
+    assert lib.ns_batch_stats(off, off, off, 4, 10, None, None, None, None, None, ws,
+                              1 << 40, None) == -1
+    agg_ok = ns.MatrixView(1024, 2048, 3072, 10, 0)
+    wv = ns.BatchMatricesView(4096, 5120, 6144, 10)
+    assert lib.ns_batch_stats(off, off, off, 4, 10, None, ctypes.byref(agg_ok), None,
+                              ctypes.byref(wv), None, ws, 1 << 40, None) == -1
+    assert lib.ns_batch_stats(off, off, off, 4, 10, None, ctypes.byref(aggm), None, None, None,
+                              ws, 1 << 40, None) == -2
+    # the batch total is below 2^32
+    big_agg = ns.MatrixView(1024, 2048, 3072, 1 << 33, 0)
+    assert lib.ns_batch_stats(off, off, off, 4, 1 << 32, None, ctypes.byref(big_agg), None, None,
+                              None, ws, 1 << 40, None) == -6
 
 
 def test_max_link_argument_errors(lib):

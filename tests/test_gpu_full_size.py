@@ -1,18 +1,21 @@
 """Full-size checks: the 2^30-packet aggregate (8192 windows of 2^17 with a
-scanner and a sink) in the benchmark's launch configuration; and, past 2^31
-packets or entries, one window, a batch of 32769 windows and a union-add, all
-with closed-form answers.
+scanner and a sink) in the benchmark's launch configuration, every output
+compared with the oracle; and, past 2^31 packets or entries, one window, a
+batch of 32769 windows and a union-add, all with closed-form answers.
 
-The oracle cannot sort 2^30 keys within a test's time, so parity here is:
-* properties that hold at any size (sorted strictly increasing keys, counts
-  >= 1 summing to 2^30, valid packets = 2^30, the invariants between the eight
-  quantities, the scanner's 2^16 distinct targets),
-* the eight quantities recomputed by the oracle from the GPU's own matrix
-  (checks the statistics pass at full size),
-* sampled rows of the matrix recomputed by the oracle from the packets of the
-  sampled sources (checks the matrix construction at full size).
+At 2^30 packets the oracle builds the aggregate in source ranges: the packets
+are cut by the top 16 bits of their source into ranges of about 2^23 packets
+(a range whose sources are one 16-bit prefix may be larger), each range's
+matrix is built by the oracle on its own host thread, and since the ranges
+are disjoint intervals of the sort key (source in the high half) their
+matrices, concatenated in range order, are the oracle's matrix of all 2^30
+packets. That matrix is compared entry by entry with the GPU's; the oracle's
+eight quantities of it with the GPU's; and every window's eight quantities
+with the oracle's, window by window.
 """
+import os
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -27,10 +30,24 @@ def say(*a):
     print("[case]", *a, file=sys.stderr, flush=True)
 
 
+def source_ranges(hist: np.ndarray, target: int):
+    """Consecutive ranges [lo, hi) of 16-bit source prefixes holding about
+    `target` packets each (a single prefix may hold more)."""
+    out, lo, acc = [], 0, 0
+    for p in range(hist.size):
+        if acc and acc + int(hist[p]) > target:
+            out.append((lo, p))
+            lo, acc = p, 0
+        acc += int(hist[p])
+    out.append((lo, hist.size))
+    return out
+
+
 def test_aggregate_2p30_full_size():
     import torch
-    from paper_2510_14050_amd import ns
+    from paper_2510_14050_amd import ns, tune
     dev = torch.device("cuda:0")
+    torch.cuda.empty_cache()
     wl = synth.aggregate_2p30()
     N = wl.total_packets
     assert N == 1 << 30
@@ -42,50 +59,85 @@ def test_aggregate_2p30_full_size():
     agg = ns.Matrix(N, device=dev)
     st = torch.zeros(8, dtype=torch.int64, device=dev)
     win_st = torch.zeros((W, 8), dtype=torch.int64, device=dev)
-    say("ns_batch_stats: 8192 windows + aggregate")
-    ns.batch_stats(src_t, dst_t, off, win_st, ws, agg=agg, agg_stats=st)
+    say("ns_batch_stats: 8192 windows + aggregate (benchmark launch shape)")
+    ns.batch_stats(src_t, dst_t, off, win_st, ws, agg=agg, agg_stats=st, tune=tune.lookup(N, W))
     torch.cuda.synchronize()
+    assert ns.device_status() == 0
     got = ns.stats_numpy(st).copy()
     per_win = ns.stats_numpy(win_st).copy()
-    v, links, ns_, nd, msp, mfo, mdp, mfi = [int(x) for x in got]
+    links = agg.nnz()
     say("stats", got.tolist())
+    say("ns_batch_stats: the aggregate alone (the benchmark's step)")
+    agg2 = ns.Matrix(N, device=dev)
+    st2 = torch.zeros(8, dtype=torch.int64, device=dev)
+    ns.batch_stats(src_t, dst_t, off, None, ws, agg=agg2, agg_stats=st2,
+                   tune=tune.lookup(N, W, aggregate_only=True))
+    torch.cuda.synchronize()
+    assert ns.device_status() == 0
+    assert ns.stats_numpy(st2).tolist() == got.tolist()
+    assert agg2.nnz() == links
+    assert torch.equal(agg2.keys[:links], agg.keys[:links])
+    assert torch.equal(agg2.counts[:links], agg.counts[:links])
+    del agg2, st2, ws
+    ns.release_graphs()
+    torch.cuda.empty_cache()
+    v, _, ns_, nd, msp, mfo, mdp, mfi = [int(x) for x in got]
     assert v == N
-    assert links <= v and links >= max(mfo, mfi)
-    assert max(ns_, nd) <= links
-    assert mfo <= min(nd, msp) and mfi <= min(ns_, mdp)
     assert mfo >= 1 << 16 and mfi >= 1 << 16   # scanner / sink reach 2^16 peers
-    say("copying the matrix to the host")
+    say("copying the matrix and the packets to the host")
     keys, counts = agg.numpy()
-    assert keys.size == links
-    assert np.all(keys[1:] > keys[:-1])
-    assert counts.min() >= 1 and int(counts.sum()) == N
-    say("oracle statistics of the GPU matrix")
-    assert oracle.stats_matrix(keys, counts).tolist() == got.tolist()
-    say("sampled windows against the oracle")
+    del agg
     src = synth.as_u32(src_t)
     dst = synth.as_u32(dst_t)
-    del src_t, dst_t
     o = wl.offsets
-    for w in [0, 1, 4095, 8191] + list(np.random.default_rng(1).integers(0, W, 8)):
-        a, b = int(o[w]), int(o[w + 1])
-        assert per_win[w].tolist() == oracle.stats(src[a:b], dst[a:b]).tolist(), w
-    assert int(per_win[:, 0].sum()) == N
-    say("sampled rows against the oracle")
-    rng = np.random.default_rng(0)
-    rows = keys >> np.uint64(32)
-    sample = np.unique(np.concatenate([
-        np.array([wl.scanner, int(wl.sources[0]), int(wl.sources[-1])], np.uint64),
-        rows[rng.integers(0, rows.size, 40)],
-        rows[:1], rows[-1:]])).astype(np.uint32)
-    pos = np.minimum(np.searchsorted(sample, src), sample.size - 1)
-    mask = sample[pos] == src
-    ok, oc = oracle.build_matrix(src[mask], dst[mask])
-    sel = np.isin(rows.astype(np.uint32), sample)
-    assert np.array_equal(keys[sel], ok)
-    assert np.array_equal(counts[sel], oc)
+    oracle.build(force=not os.path.exists(oracle.LIB))
+    oracle.stats(src[:1], dst[:1])  # load the library before the threads start
+    threads = min(16, os.cpu_count() or 1)
+    pool = ThreadPoolExecutor(threads)
+    # every window's quantities, 64 windows per task
+    win_jobs = [pool.submit(oracle.stats_windows, src[int(o[a]):int(o[min(a + 64, W)])],
+                            dst[int(o[a]):int(o[min(a + 64, W)])],
+                            o[a:min(a + 64, W) + 1] - o[a]) for a in range(0, W, 64)]
+    say("cutting the packets into source ranges on the device")
+    s64 = src_t.to(torch.int64) & 0xFFFFFFFF
+    hist = torch.bincount(s64 >> 16, minlength=1 << 16).cpu().numpy()
+    ranges = source_ranges(hist, 1 << 23)
+    order = sorted(range(len(ranges)), key=lambda i: -int(hist[ranges[i][0]:ranges[i][1]].sum()))
+    jobs = [None] * len(ranges)
+    for i in order:  # largest ranges first, so the longest sorts start early
+        lo, hi = ranges[i]
+        m = (s64 >= (lo << 16)) & (s64 < (hi << 16))
+        bs, bd = synth.as_u32(src_t[m]), synth.as_u32(dst_t[m])
+        assert bs.size == int(hist[lo:hi].sum())
+        jobs[i] = pool.submit(oracle.build_matrix, bs, bd)
+    del s64, m, src_t, dst_t
+    torch.cuda.empty_cache()
+    say(len(ranges), "source ranges; comparing the matrix range by range")
+    ok_keys, ok_counts = [], []
+    for (lo, hi), j in zip(ranges, jobs):
+        k, c = j.result()
+        a = int(np.searchsorted(keys, np.uint64(lo) << np.uint64(48)))
+        b = int(np.searchsorted(keys, np.uint64(hi) << np.uint64(48))) if hi < (1 << 16) \
+            else keys.size
+        assert np.array_equal(keys[a:b], k), (lo, hi)
+        assert np.array_equal(counts[a:b], c), (lo, hi)
+        ok_keys.append(k)
+        ok_counts.append(c)
+    assert sum(k.size for k in ok_keys) == keys.size == links
+    say("the oracle's eight quantities of its own matrix")
+    ok_k, ok_c = np.concatenate(ok_keys), np.concatenate(ok_counts)
+    del ok_keys, ok_counts
+    want = oracle.stats_matrix(ok_k, ok_c)
+    assert want.tolist() == got.tolist()
+    say("every window's quantities")
+    want_win = np.concatenate([j.result() for j in win_jobs])
+    pool.shutdown()
+    assert want_win.shape == per_win.shape
+    bad = np.nonzero(np.any(want_win != per_win, axis=1))[0]
+    assert bad.size == 0, bad[:10]
     # the scanner row: exactly 2^16 distinct targets, 1% of every window's packets
-    srow = keys[rows == np.uint64(wl.scanner)]
-    assert srow.size == 1 << 16
+    rows = keys >> np.uint64(32)
+    assert int(np.count_nonzero(rows == np.uint64(wl.scanner))) == 1 << 16
     assert int(counts[rows == np.uint64(wl.scanner)].sum()) == 8192 * wl.scan_count(1 << 17)
 
 

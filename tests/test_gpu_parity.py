@@ -98,12 +98,13 @@ def test_patterns(gpu, name, src, dst):
     build_and_check(torch, ns, src, dst)
 
 
-def run_batch(torch, ns, src, dst, sizes, graph=True, agg=True, win=True, tune=None, ws=None):
+def run_batch(torch, ns, src, dst, sizes, graph=True, agg=True, win=True, tune=None, ws=None,
+              windows=True):
     off = np.zeros(len(sizes) + 1, np.int64)
     np.cumsum(sizes, out=off[1:])
     N, W = int(off[-1]), len(sizes)
     ws = ws or ns.Workspace(N, W)
-    out = torch.full((W, 8), -1, dtype=torch.int64, device="cuda")
+    out = torch.full((W, 8), -1, dtype=torch.int64, device="cuda") if windows else None
     m = ns.Matrix(N) if agg else None
     ms = torch.full((8,), -1, dtype=torch.int64, device="cuda") if agg else None
     wm = ns.BatchMatrices(N, W) if win else None
@@ -114,10 +115,11 @@ def run_batch(torch, ns, src, dst, sizes, graph=True, agg=True, win=True, tune=N
 
 
 def check_batch(ns, src, dst, off, out, m, ms, wm):
-    want = oracle.stats_windows(src, dst, off.astype(np.uint64))
-    got = ns.stats_numpy(out)
-    bad = np.nonzero((got != want).any(axis=1))[0]
-    assert bad.size == 0, f"windows {bad[:5]}: got {got[bad[:2]]} want {want[bad[:2]]}"
+    if out is not None:
+        want = oracle.stats_windows(src, dst, off.astype(np.uint64))
+        got = ns.stats_numpy(out)
+        bad = np.nonzero((got != want).any(axis=1))[0]
+        assert bad.size == 0, f"windows {bad[:5]}: got {got[bad[:2]]} want {want[bad[:2]]}"
     if m is not None:
         k, c = m.numpy()
         ok, oc = oracle.build_matrix(src, dst)
@@ -204,6 +206,24 @@ def test_batch_aggregate_window_counts(gpu, W, graph):
     for win in (True, False):
         res = run_batch(torch, ns, src, dst, sizes, graph=graph, win=win)
         check_batch(ns, src, dst, *res)
+
+
+@pytest.mark.parametrize("graph", [True, False], ids=["graph", "eager"])
+@pytest.mark.parametrize("case", ["one", "two", "ragged", "w129", "all_empty", "chunked"])
+def test_batch_aggregate_alone(gpu, case, graph):
+    """ns_batch_stats with the aggregate as its only output (no per-window
+    quantities): the aggregate's matrix and quantities against the oracle,
+    for one window, several, ragged and empty ones, and the chunked passes."""
+    torch, ns = gpu
+    rng = np.random.default_rng(77)
+    sizes = {"one": [70_001], "two": [4097, 12_345], "ragged": RAGGED,
+             "w129": [int(x) for x in rng.integers(0, 2000, 129)], "all_empty": [0, 0, 0],
+             "chunked": [100_000, 0, 33_333]}[case]
+    t = ns.tuning(chunked_min=1) if case == "chunked" else None
+    say("aggregate alone", case, "graph" if graph else "eager")
+    src, dst = zipf_packets(900 + len(sizes), sum(sizes), pool=1500)
+    res = run_batch(torch, ns, src, dst, sizes, graph=graph, win=False, windows=False, tune=t)
+    check_batch(ns, src, dst, *res)
 
 
 CHUNKED_CASES = {

@@ -128,3 +128,51 @@ def test_serving_memory_budget_gates_admission():
         assert r.rolling_stats.tolist() == want_roll[k].tolist(), k
     with pytest.raises(ValueError):
         Server(ring=ring, max_window=mw, max_batch=2, budget_bytes=budget - 1)
+
+
+@pytest.mark.gpu
+@pytest.mark.slow
+def test_serving_at_scale_every_arrival():
+    """Serving near the full configuration's shape: a ring of 256 windows of
+    2^10..2^15 packets (Zipf 1.2 over a pool of 2^20), Poisson arrivals at
+    2000 windows/s, hash tables small enough that the rolling state is
+    compacted several times. Every arrival's window quantities and rolling
+    quantities (windows k-255..k by arrival order) equal the oracle's, served
+    in the mix and served alone (one window at a time)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+    from paper_2510_14050_amd.serve import Server
+    ring, n = 256, 800
+    wl = synth.Workload("serve_scale_t", 11, 1 << 20, 1.2, 1.2,
+                        synth.log_uniform_sizes(11, n, 10, 15))
+    wins = [wl.window(w) for w in range(n)]
+    say("oracle: every window and every rolling aggregate of", n, "arrivals")
+    oracle.stats(wins[0][0][:1], wins[0][1][:1])
+
+    def rolling(k):
+        lo = max(0, k - ring + 1)
+        return oracle.stats(np.concatenate([wins[j][0] for j in range(lo, k + 1)]),
+                            np.concatenate([wins[j][1] for j in range(lo, k + 1)]))
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        roll_jobs = [ex.submit(rolling, k) for k in range(n)]
+        want_win = list(ex.map(lambda w: oracle.stats(*w), wins))
+        want_roll = [j.result() for j in roll_jobs]
+    kw = dict(ring=ring, max_window=1 << 15, budget_bytes=256 << 20,
+              link_slots=1 << 23, address_slots=1 << 22)
+    arr = synth.poisson_arrivals(12, n, 2000.0)
+    say("serve in the mix (Poisson arrivals, micro-batches of up to 16)")
+    rep_mix = Server(max_batch=16, **kw).run(wins, arrivals_s=arr - arr[0])
+    say("serve alone (one window at a time)")
+    rep_alone = Server(max_batch=1, **kw).run(wins)
+    torch.cuda.synchronize()
+    for rep in (rep_mix, rep_alone):
+        for k, r in enumerate(rep.results):
+            assert r.seq == k
+            assert r.window_stats.tolist() == want_win[k].tolist(), k
+            assert r.rolling_stats.tolist() == want_roll[k].tolist(), k
+        assert rep.compactions >= 2, rep.compactions
+    s = rep_mix.summary()
+    say("in the mix:", {k: s[k] for k in ("p50_ms", "p99_ms", "mean_batch", "max_in_flight")},
+        "compactions", rep_mix.compactions)
