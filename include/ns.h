@@ -219,12 +219,15 @@ int ns_batch_stats_eager(const uint32_t *src, const uint32_t *dst, const uint64_
 
 /* Rolling aggregate for serving (the running union-add of the windows added
  * minus the windows removed), kept in device hash tables so that an update
- * costs time proportional to the entries of the windows involved, not to the
- * aggregate. Layout: one caller-owned device buffer `mem` of `bytes` >=
- * ns_rolling_size(...); link_slots and address_slots are powers of two (hash
- * slots for distinct links and for distinct sources / destinations; keep live
- * entries plus those added since the last compaction below ~60% of them). The
- * state holds fewer than 2^32 packets. */
+ * costs time proportional to the entries of the windows involved plus one
+ * scan of the source and destination tables (16 bytes per address slot, for
+ * the four maxima), not to the links of the aggregate. Layout: one
+ * caller-owned device buffer `mem` of `bytes` >= ns_rolling_size(...);
+ * link_slots and address_slots are powers of two (hash slots for distinct
+ * links and for distinct sources / destinations; keep live entries plus those
+ * added since the last compaction below ~60% of them). The state holds fewer
+ * than 2^32 packets: an add that would wrap a link's or an address's 32-bit
+ * packet count is reported by ns_device_status (NS_ERR_CAPACITY). */
 typedef struct {
   void *mem;
   uint64_t bytes;

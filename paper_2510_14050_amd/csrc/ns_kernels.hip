@@ -1184,7 +1184,9 @@ void k_runs(RunArgs a) {
 // whatever their contents. Keys must increase strictly over the whole matrix,
 // values must lie in [1, 2^32) (the column items hold a count in 32 bits; with
 // fewer than 2^32 entries their sum then cannot wrap) and row_ptr must run
-// from 0 to nnz: a violation raises the device status (invalid argument).
+// from 0 to nnz without decreasing (every row pointer is also compared with
+// the next one, in a grid-stride sweep over the rows): a violation raises
+// the device status (invalid argument).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_csr_expand(const uint32_t *rows, const uint64_t *row_ptr,
                                                     uint64_t nrows, const uint32_t *cols,
@@ -1225,6 +1227,9 @@ __global__ __launch_bounds__(256) void k_csr_expand(const uint32_t *rows, const 
       counts[e] = c;
     }
   }
+  for (uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x; r < nrows;
+       r += (uint64_t)gridDim.x * 256)
+    bad |= row_ptr[r] > row_ptr[r + 1];
   if (bad) atomicOr(&g_status, 4);
 }
 

@@ -19,7 +19,8 @@
 // source and destination tables after each update. All counters change by
 // atomics whose sums commute, so adds and removes of one update may run in any
 // order. Every count stays below 2^32 (the state holds fewer than 2^32
-// packets).
+// packets); an add that wraps a link or address packet count raises the
+// device status (capacity).
 // Included at the end of ns_kernels.hip, whose device error word it sets.
 #include "ns_device.h"
 #include "ns_launch.h"
@@ -77,6 +78,7 @@ __device__ void address_update(const RollTables &t, bool src_side, uint32_t addr
   }
   if (plus) {
     const uint32_t old = atomicAdd(pk + s, dp);
+    if (old + dp < old) flag_status(2);  // the 32-bit packet count wrapped
     if (old == 0 && dp) atomicAdd(live, 1ull);
   } else {
     const uint32_t old = atomicSub(pk + s, dp);
@@ -110,6 +112,7 @@ __global__ __launch_bounds__(256) void k_roll_update(RollTables t, RollDelta d) 
     int dfan = 0;
     if (plus) {
       const uint32_t old = atomicAdd(cnt, c);
+      if (old + c < old) flag_status(2);  // the 32-bit link count wrapped
       atomicAdd((unsigned long long *)&t.hdr->packets, (unsigned long long)c);
       if (old == 0) {
         atomicAdd((unsigned long long *)&t.hdr->links, 1ull);

@@ -125,6 +125,32 @@ def test_csr_bad_input_is_reported(gpu):
     assert ns.device_status() == 0  # reading clears the word
 
 
+def test_csr_decreasing_row_pointers_are_reported(gpu):
+    """Row pointers that run from 0 to nnz but decrease somewhere (so entries
+    would land in other rows) raise the device status; so does a row pointer
+    past nnz in the middle, and a decrease between two stored empty rows."""
+    torch, ns = gpu
+    say("csr decreasing row pointers")
+    rows = np.array([5, 9], np.uint32)
+    cols = np.array([1, 2], np.uint32)
+    vals = np.array([1, 1], np.uint64)
+    run_csr(torch, ns, rows, np.array([0, 3, 2], np.uint64), cols, vals, 2)
+    assert ns.device_status() == -1
+    run_csr(torch, ns, rows, np.array([0, 1, 2], np.uint64), cols, vals, 2)
+    assert ns.device_status() == 0
+    src, dst = packets(35, 4000, 80)
+    k, c = oracle.build_matrix(src, dst)
+    rows, row_ptr, cols, vals = to_csr(k, c, empty_rows=[7, 8, 0xFFFFFFF0])
+    got = run_csr(torch, ns, rows, row_ptr, cols, vals, src.size)
+    assert ns.device_status() == 0
+    assert got == oracle.stats_matrix(k, c).tolist()
+    for r in (1, rows.size // 2, rows.size - 1):
+        bad = row_ptr.copy()
+        bad[r] = bad[r + 1] + 1  # row_ptr[r] > row_ptr[r + 1]
+        run_csr(torch, ns, rows, bad, cols, vals, src.size)
+        assert ns.device_status() == -1, r
+
+
 def test_csr_value_range_and_total_are_checked(gpu):
     """Values must lie in [1, 2^32) and sum to at most the caller's packet
     bound: a value of 2^32, two values whose 64-bit sum wraps around, a sum
