@@ -138,6 +138,22 @@ int ns_accumulate_workspace_size(uint64_t na, uint64_t nb, uint64_t *bytes);
 int ns_accumulate(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
                   ns_matrix_t *acc_out, void *ws, uint64_t ws_bytes, void *stream);
 
+/* ns_accumulate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same union-add / subtract with the same arguments and results, but the
+ * merge's ticket and look-back words live in a scratch array the library
+ * holds in device memory (one per device, about 4 MiB, kept until the process
+ * ends) instead of a caller workspace. No call allocates or frees memory.
+ * Supports na + nb <= NS_ACCUMULATE_NOALLOC_MAX_ENTRIES (na, nb as for
+ * ns_accumulate); larger inputs return NS_ERR_UNSUPPORTED before anything is
+ * enqueued. Every call on a device uses that device's one scratch array (it
+ * is cleared by kernels at the start of each call): calls that may overlap on
+ * one device, such as calls on different streams without ordering between
+ * them, race and give undefined results. */
+#define NS_ACCUMULATE_NOALLOC_MAX_ENTRIES (1ull << 30)
+int ns_accumulate_noalloc(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
+                          ns_matrix_t *acc_out, void *stream);
+
 /* Out-of-core build (Sec. III-C "Concurrent Batching", Fig. 3: input data
  * held on the host is cut into b_n batches that are moved to the GPU one
  * after the other during the computation). The n packets in HOST memory

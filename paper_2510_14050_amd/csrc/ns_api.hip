@@ -671,11 +671,46 @@ std::string batch_key(int dev, const BatchArgs &b, void *ws, uint64_t ws_bytes) 
   return std::string(buf);
 }
 
+// Library-owned scratch of ns_accumulate_noalloc: the merge's ticket and
+// look-back words for up to NS_ACCUMULATE_NOALLOC_MAX_ENTRIES merged entries,
+// in a file-scope device array (each device holds its own copy for the life
+// of the process). Host code never uses the array's name as an address: the
+// device address comes from hipGetSymbolAddress, once per device.
+// Same carve-up as merge_plan: the ticket in the first 256 bytes, then the
+// look-back words rounded up to 256 bytes.
+constexpr uint64_t kScratchBytes =
+    kAlign + ((NS_ACCUMULATE_NOALLOC_MAX_ENTRIES / kMergeTile + 2) * 8 + kAlign - 1) / kAlign * kAlign;
+
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+
+int scratch_address(void **out) {
+  static std::mutex mu;
+  static void *addr[64] = {};
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return NS_ERR_HIP;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || reinterpret_cast<uintptr_t>(p) % kAlign) return NS_ERR_HIP;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return NS_OK;
+}
+
 // Union-add / subtract of two sorted COO matrices into acc_out (the checks
 // and kernel sequence of ns_accumulate) with the merge's ticket and look-back
-// words in the caller's `ws`.
+// words in the caller's `ws`, or, with `noalloc`, in the library's scratch
+// array (its address is taken only after the host-side checks passed).
 int accumulate_into(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
-                    ns_matrix_t *acc_out, void *ws, uint64_t ws_bytes, hipStream_t s) {
+                    ns_matrix_t *acc_out, void *ws, uint64_t ws_bytes, hipStream_t s,
+                    bool noalloc) {
   if (!acc_in || !win || !acc_out) return NS_ERR_INVALID_ARG;
   if (sign != 1 && sign != -1) return NS_ERR_INVALID_ARG;
   const ns_matrix_t *ins[2] = {acc_in, win};
@@ -692,6 +727,13 @@ int accumulate_into(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
   const uint64_t need = sign > 0 ? na + nb : na;
   if (acc_out->capacity < need) return NS_ERR_CAPACITY;
   const MergeLayout ML = merge_plan(na + nb);
+  if (noalloc) {
+    if (na + nb > NS_ACCUMULATE_NOALLOC_MAX_ENTRIES || ML.total > kScratchBytes)
+      return NS_ERR_UNSUPPORTED;
+    const int rc = scratch_address(&ws);
+    if (rc) return rc;
+    ws_bytes = kScratchBytes;
+  }
   if (!ws || reinterpret_cast<uintptr_t>(ws) % kAlign) return NS_ERR_WORKSPACE;
   if (ws_bytes < ML.total) return NS_ERR_WORKSPACE;
   const uint64_t tiles = ML.tiles;
@@ -717,7 +759,8 @@ int accumulate_into(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
   a.sign = sign;
   a.lb = lbs;
   a.ticket = ticket;
-  HIP_TRY(timed(K_MERGE, s, [&] { return launch_merge(a, tiles, s); }));
+  if (noalloc) HIP_TRY(launch_merge(a, tiles, s));  // no timing events either
+  else HIP_TRY(timed(K_MERGE, s, [&] { return launch_merge(a, tiles, s); }));
   acc_out->packets = sign > 0 ? acc_in->packets + win->packets : acc_in->packets - win->packets;
   return NS_OK;
 }
@@ -854,7 +897,13 @@ int ns_accumulate_workspace_size(uint64_t na, uint64_t nb, uint64_t *bytes) {
 int ns_accumulate(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
                   ns_matrix_t *acc_out, void *ws, uint64_t ws_bytes, void *stream) {
   return accumulate_into(acc_in, win, sign, acc_out, ws, ws_bytes,
-                         static_cast<hipStream_t>(stream));
+                         static_cast<hipStream_t>(stream), false);
+}
+
+int ns_accumulate_noalloc(const ns_matrix_t *acc_in, const ns_matrix_t *win, int sign,
+                          ns_matrix_t *acc_out, void *stream) {
+  return accumulate_into(acc_in, win, sign, acc_out, nullptr, 0,
+                         static_cast<hipStream_t>(stream), true);
 }
 
 int ns_stream_workspace_size(uint64_t batch, uint64_t capacity, uint64_t *bytes) {

@@ -63,7 +63,7 @@ class BatchMatricesView(ctypes.Structure):
 
 
 EXPORTS = ("ns_workspace_size", "ns_build_matrix", "ns_accumulate_workspace_size",
-           "ns_accumulate", "ns_stats",
+           "ns_accumulate", "ns_accumulate_noalloc", "ns_stats",
            "ns_stream_workspace_size", "ns_build_matrix_streamed",
            "ns_stats_csr_workspace_size", "ns_stats_csr",
            "ns_batch_stats", "ns_batch_stats_eager", "ns_max_link_packets",
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
     lib.ns_workspace_size.argtypes = [U64, U32, ctypes.POINTER(U64)]
     lib.ns_build_matrix.argtypes = [P, P, U64, PM, P, U64, P]
     lib.ns_accumulate.argtypes = [PM, PM, I, PM, P, U64, P]
+    lib.ns_accumulate_noalloc.argtypes = [PM, PM, I, PM, P]
     lib.ns_stream_workspace_size.argtypes = [U64, U64, ctypes.POINTER(U64)]
     lib.ns_accumulate_workspace_size.argtypes = [U64, U64, ctypes.POINTER(U64)]
     lib.ns_stats_csr_workspace_size.argtypes = [U64, ctypes.POINTER(U64)]
@@ -306,6 +307,22 @@ def accumulate(acc_in: Matrix, win: Matrix, sign: int, acc_out: Matrix,
                                 ws.ptr, ws.nbytes, _stream(stream)), "ns_accumulate")
     acc_out.packets = int(c.packets)
     return acc_out
+
+
+def accumulate_noalloc(acc_in: Matrix, win: Matrix, sign: int, acc_out: Matrix, stream=None):
+    """ns_accumulate_noalloc: the same union-add / subtract as accumulate(),
+    with the library's own device scratch instead of a caller workspace (no
+    device memory is allocated; calls that overlap on one device race)."""
+    a, b, c = acc_in.view(), win.view(), acc_out.view()
+    _check(load().ns_accumulate_noalloc(ctypes.byref(a), ctypes.byref(b), int(sign),
+                                        ctypes.byref(c), _stream(stream)),
+           "ns_accumulate_noalloc")
+    acc_out.packets = int(c.packets)
+    return acc_out
+
+
+# largest na + nb that ns_accumulate_noalloc accepts (NS_ACCUMULATE_NOALLOC_MAX_ENTRIES)
+ACCUMULATE_NOALLOC_MAX_ENTRIES = 1 << 30
 
 
 def stats(m: Matrix, out, ws: Workspace, stream=None):
