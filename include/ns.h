@@ -18,7 +18,8 @@
  *     are untouched. No device-to-host synchronisation happens on any hot path:
  *     capacities are checked against host-known bounds (packet counts), and
  *     sizes produced on the device (nnz) stay on the device.
- *   - Packet counts per window / per matrix must be below 2^32.
+ *   - Packets per window and per batched call must be below 2^32; a matrix
+ *     given to ns_stats may hold more (with fewer than 2^32 + 1 entries).
  *   - `ws` is caller workspace of at least ns_workspace_size() bytes, 256-byte
  *     aligned. Calls that share one workspace must be ordered on one stream.
  */
@@ -38,7 +39,8 @@ enum {
   NS_ERR_WORKSPACE = -3,    /* ws too small or misaligned */
   NS_ERR_HIP = -4,          /* a HIP runtime call failed */
   NS_ERR_UNDERFLOW = -5,    /* subtraction below zero (host-detected, or via ns_device_status) */
-  NS_ERR_UNSUPPORTED = -6   /* size beyond the supported range (>= 2^32 packets) */
+  NS_ERR_UNSUPPORTED = -6,  /* size beyond the supported range (>= 2^32 packets) */
+  NS_ERR_BOUNDS = -7        /* an index outside its array (libns_debug.so only, via ns_device_status) */
 };
 
 /* The eight quantities, all exact uint64, in this fixed order (64 bytes).
@@ -81,7 +83,12 @@ typedef struct {
  * default; the autotuner in the Python package fills these from its cache.
  *   sort_block   workgroup size of the radix passes (256 or 512)
  *   sort_items   keys per thread in a radix pass (8 or 16): tile = block*items
- *   digit_bits   radix digit width (8)
+ *   digit_bits   radix digit width of the chunked passes (8 or 11): a single
+ *                segment on chunked passes sorts its 64-bit keys in 8 passes of
+ *                byte digits or 6 of 11-bit digits (2048 bins), and its 32-bit
+ *                column keys in 4 or 3; passes with look-back (several segments)
+ *                always use byte digits (their per-segment histograms and
+ *                per-tile look-back words grow with the bin count)
  *   scan_items   positions per thread in the run-length / run-reduce passes (4, 8 or 16)
  *   chunked_min  a single segment (one window, or the aggregate of all windows)
  *                of at least this many keys is sorted by chunked passes (count,
@@ -156,9 +163,12 @@ int ns_accumulate_noalloc(const ns_matrix_t *acc_in, const ns_matrix_t *win, int
 
 /* Out-of-core build (Sec. III-C "Concurrent Batching", Fig. 3: input data
  * held on the host is cut into b_n batches that are moved to the GPU one
- * after the other during the computation). The n packets in HOST memory
- * (src, dst: n uint32 each; page-locked memory lets the copies overlap the
- * kernels) are taken in b_n = ceil(n / batch) sub-partitions of `batch`
+ * after the other during the computation). The n packets in PAGE-LOCKED HOST
+ * memory (src, dst: n uint32 each, allocated with hipHostMalloc or torch's
+ * pin_memory; pageable memory is rejected with NS_ERR_INVALID_ARG, since an
+ * asynchronous copy of a large pageable range would have the runtime lock the
+ * existing pages, which hosts may refuse) are taken in
+ * b_n = ceil(n / batch) sub-partitions of `batch`
  * packets: sub-partition k+1 is copied to the device on `copy_stream` while
  * sub-partition k is built into its matrix on `stream` (as ns_build_matrix),
  * which is then union-added into the running aggregate (as ns_accumulate).
@@ -173,6 +183,8 @@ int ns_accumulate_noalloc(const ns_matrix_t *acc_in, const ns_matrix_t *win, int
  *   ws, ws_bytes device workspace of ns_stream_workspace_size(batch,
  *                out->capacity) bytes (256-byte aligned)
  *   copy_stream  stream of the host-to-device copies (NULL: `stream`); the
+ *                first copies wait for the work already enqueued on `stream`,
+ *                so calls sharing a workspace may be issued back to back; the
  *                host memory must stay valid until `stream` has completed
  * Not capturable into a graph (it orders two streams with events). */
 int ns_stream_workspace_size(uint64_t batch, uint64_t capacity, uint64_t *bytes);
@@ -181,7 +193,10 @@ int ns_build_matrix_streamed(const uint32_t *src, const uint32_t *dst, uint64_t 
                              void *copy_stream);
 
 /* The eight quantities of a matrix (Table I with the row/column-sum maxima)
- * into *out (device). m->packets must be below 2^32. */
+ * into *out (device). A matrix of 2^32 packets or more (such as the aggregate
+ * of an out-of-core build) is reduced with 64-bit run sums; it must then hold
+ * at most 2^32 entries (min(capacity, packets) <= 2^32), else
+ * NS_ERR_UNSUPPORTED. */
 int ns_stats(const ns_matrix_t *m, ns_stats_t *out, void *ws, uint64_t ws_bytes, void *stream);
 
 /* The eight quantities of a matrix given in hypersparse CSR form, the form
@@ -267,8 +282,10 @@ int ns_rolling_update(const ns_rolling_t *r, const ns_matrix_t *add, const ns_ma
 int ns_rolling_compact(const ns_rolling_t *from, const ns_rolling_t *to, void *stream);
 
 /* Synchronises `stream`, then reads and clears the current device's error
- * word: *status (host) = NS_OK, NS_ERR_UNDERFLOW, NS_ERR_CAPACITY or
- * NS_ERR_INVALID_ARG (a CSR input out of order), in that priority. */
+ * word: *status (host) = NS_OK, NS_ERR_BOUNDS (an index outside its array; the
+ * bounds-checked build libns_debug.so only), NS_ERR_UNDERFLOW,
+ * NS_ERR_CAPACITY or NS_ERR_INVALID_ARG (a CSR input out of order), in that
+ * priority. */
 int ns_device_status(void *stream, int *status);
 
 /* Largest link count max_ij A(i,j) of a matrix: the "maximum link counts"

@@ -19,17 +19,27 @@ FLAGS = [
 ]
 
 
+DEBUG_LIB = os.path.join(HERE, "libns_debug.so")
+
+
 def build_library(verbose: bool = False) -> str:
+    """libns.so, and libns_debug.so with every scatter / gather index of the
+    radix passes and run scans checked against its bound (compiled side by side)."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *srcs, "-o", tmp]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libns.so")
-    if verbose:
-        sys.stderr.write(r.stderr)
-    os.replace(tmp, LIB)
+    jobs = []
+    for out, extra in ((LIB, []), (DEBUG_LIB, ["-DNS_BOUNDS_CHECK=1"])):
+        tmp = out + ".tmp"
+        cmd = [HIPCC, *FLAGS, *extra, *srcs, "-o", tmp]
+        jobs.append((out, tmp, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                                stderr=subprocess.PIPE, text=True)))
+    for out, tmp, p in jobs:
+        so, se = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(so + se)
+            raise RuntimeError(f"hipcc failed building {os.path.basename(out)}")
+        if verbose:
+            sys.stderr.write(se)
+        os.replace(tmp, out)
     return LIB
 
 

@@ -20,7 +20,9 @@ namespace {
 constexpr uint64_t kAlign = 256;
 constexpr int kMaxTickets = 64;
 // A single segment of at least this many keys is sorted by chunked passes
-// (reduce, scan, scatter) instead of passes with look-back.
+// (reduce, scan, scatter) instead of passes with look-back. The autotuner
+// chooses per size class (on MI355X the passes with look-back were faster for
+// single segments of 2^24 .. 2^30 keys).
 #ifndef NS_CHUNKED_MIN
 #define NS_CHUNKED_MIN (1ull << 24)
 #endif
@@ -78,10 +80,12 @@ Layout plan(uint64_t N, uint32_t W) {
   L.lb0 = take(L.sort_tiles * kBins * 8);
   L.lb1 = take(L.sort_tiles * kBins * 8);
   L.lbs = take(L.scan_tiles * 2 * 8);
+  // chunk tables sized for the widest digit (2048 bins); byte digits use the
+  // first 256 entries of each row
   L.chunk_rows = chunk_rows(N, kChunkTile);
-  L.ccount = take(L.chunk_rows * kBins * 4);
-  L.cprefix = take((L.chunk_rows + 1) * kBins * 8);  // + digit totals
-  L.cbsum = take((uint64_t)kChunkBlocks * kBins * 8);
+  L.ccount = take(L.chunk_rows * kMaxBins * 4);
+  L.cprefix = take((L.chunk_rows + 1) * kMaxBins * 8);  // + digit totals
+  L.cbsum = take((L.chunk_rows < kChunkBlocks ? L.chunk_rows : kChunkBlocks) * kMaxBins * 8);
   L.KA = take((N + 1) * 8);
   L.KB = take((N + 1) * 8);
   L.HA = take((N + 2) * 8);
@@ -107,7 +111,7 @@ ChunkArgs chunk_args(const Ws &ws, const uint64_t *seg_off) {
   c.max_chunks = (uint32_t)ws.L.chunk_rows;
   c.count = ws.at<uint32_t>(ws.L.ccount);
   c.prefix = ws.at<uint64_t>(ws.L.cprefix);
-  c.total = ws.at<uint64_t>(ws.L.cprefix) + ws.L.chunk_rows * kBins;
+  c.total = ws.at<uint64_t>(ws.L.cprefix) + ws.L.chunk_rows * kMaxBins;
   c.bsum = ws.at<uint64_t>(ws.L.cbsum);
   return c;
 }
@@ -206,6 +210,7 @@ struct Shapes {
   SortShape sort;
   ScanShape scan;
   uint64_t chunked_min = kChunkedMin;
+  int digit_bits = 8;  // digit width of the chunked passes (8 or kWideBits)
   // chunked passes: the largest tile measured fastest (fewest tiles per chunk
   // boundary, most keys per digit run)
   SortShape chunk = {kChunkBlock, kChunkItems};
@@ -215,8 +220,10 @@ int resolve_tuning(const ns_tuning_t *t, Shapes *sh) {
   sh->sort = {256, 16};
   sh->scan = {8};
   sh->chunked_min = kChunkedMin;
+  sh->digit_bits = 8;
   if (!t) return NS_OK;
-  if (t->digit_bits && t->digit_bits != 8) return NS_ERR_INVALID_ARG;
+  if (t->digit_bits && t->digit_bits != 8 && t->digit_bits != kWideBits) return NS_ERR_INVALID_ARG;
+  if (t->digit_bits) sh->digit_bits = (int)t->digit_bits;
   if (t->sort_block) {
     if (t->sort_block != 256 && t->sort_block != 512) return NS_ERR_INVALID_ARG;
     sh->sort.block = (int)t->sort_block;
@@ -241,7 +248,7 @@ int resolve_tuning(const ns_tuning_t *t, Shapes *sh) {
 // ... ends in items_in).
 int enqueue_columns(Ws &ws, const Shapes &sh, uint64_t *items, uint64_t *tmp,
                     const uint64_t *link_off, uint32_t W, uint64_t max_items, uint64_t *stats,
-                    hipStream_t s) {
+                    hipStream_t s, const uint64_t *gather = nullptr) {
   const Layout &L = ws.L;
   uint64_t *t_csort = ws.at<uint64_t>(L.t_csort), *t_run = ws.at<uint64_t>(L.t_run);
   uint32_t *chist = ws.at<uint32_t>(L.chist), *cbase = ws.at<uint32_t>(L.cbase);
@@ -269,16 +276,20 @@ int enqueue_columns(Ws &ws, const Shapes &sh, uint64_t *items, uint64_t *tmp,
   const uint64_t sort_tiles = max_items / sh.sort.tile() + W + 1;
   uint64_t *lb[2] = {ws.at<uint64_t>(L.lb0), ws.at<uint64_t>(L.lb1)};
   uint64_t *buf[2] = {items, tmp};
+  // the 32-bit destination in digits of `bits` bits, least significant first
+  const int bits = chunked ? sh.digit_bits : 8;
+  const int passes = (32 + bits - 1) / bits;
   HIP_TRY(timed(chunked ? K_CPASS_CHUNKED : K_CPASS, s, [&] {
-    for (int q = 0; q < kColDigits; ++q) {
+    for (int q = 0; q < passes; ++q) {
       PassArgs a{};
       a.in = buf[q & 1];
       a.out = buf[(q + 1) & 1];
-      a.shift = 32 + 8 * q;
+      a.shift = 32 + bits * q;
       a.ticket = ws.ticket();
+      a.lim = max_items;
       if (chunked) {
         const ChunkArgs c = chunk_args(ws, link_off);
-        const hipError_t e = launch_pass_chunked(sh.chunk, a, c, max_items, K_CHUNK_COUNT, s);
+        const hipError_t e = launch_pass_chunked(sh.chunk, a, c, max_items, bits, K_CHUNK_COUNT, s);
         if (e != hipSuccess) return e;
         continue;
       }
@@ -293,10 +304,10 @@ int enqueue_columns(Ws &ws, const Shapes &sh, uint64_t *items, uint64_t *tmp,
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
-  }, kColDigits));
-  // 4 passes: sorted items are back in `items`
+  }, passes));
+  // an even number of passes leaves the sorted items in `items`, an odd one in `tmp`
   RunArgs r{};
-  r.keys = items;
+  r.keys = buf[passes & 1];
   r.seg_off = link_off;
   r.tile_off = t_run;
   r.W = W;
@@ -305,6 +316,9 @@ int enqueue_columns(Ws &ws, const Shapes &sh, uint64_t *items, uint64_t *tmp,
   r.head_off = col_off;
   r.lb = lbs;
   r.ticket = ws.ticket();
+  r.wide = gather != nullptr;  // items carry link indices; counts come from `gather`
+  r.gather = gather;
+  r.lim = max_items;
   HIP_TRY(timed(K_RUNS, s, [&] { return launch_runs(sh.scan, 1, r, run_tiles, s); }));
   // fan-in = run length, destination packets = run sum
   HIP_TRY(timed(K_SEGMAX, s, [&] { return launch_segmax(hpos, hval, col_off, W, max_items, stats, 7, 6, s); }));
@@ -363,8 +377,11 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
     HIP_TRY(timed(K_HIST, s, [&] { return launch_hist_packets(src, dst, seg_off, t_hist, W, hist_tiles, hist, s); }));
     HIP_TRY(timed(K_HSCAN, s, [&] { return launch_hist_scan(hist, base, (uint64_t)W * kKeyDigits, s); }));
   }
-  // 8 stable byte passes, least significant first; pass p writes buf[p & 1]
+  // stable passes over digits of `bits` bits, least significant first (8 byte
+  // digits, or 6 of 11 bits for a chunked single segment); pass p writes buf[p & 1]
   uint64_t *buf[2] = {o.sort_a, o.sort_b};
+  const int bits = chunked ? sh.digit_bits : 8;
+  const int passes = (64 + bits - 1) / bits;
   auto pass = [&](int p) {
     PassArgs a{};
     if (p == 0) {
@@ -374,11 +391,12 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
       a.in = buf[(p - 1) & 1];
     }
     a.out = buf[p & 1];
-    a.shift = 8 * p;
+    a.shift = bits * p;
     a.ticket = ws.ticket();
+    a.lim = N;
     if (chunked) {
       const ChunkArgs c = chunk_args(ws, seg_off);
-      return launch_pass_chunked(sh.chunk, a, c, N, K_CHUNK_COUNT, s);
+      return launch_pass_chunked(sh.chunk, a, c, N, bits, K_CHUNK_COUNT, s);
     }
     a.seg_off = seg_off;
     a.tile_off = t_sort;
@@ -391,13 +409,13 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
   };
   HIP_TRY(timed(chunked ? K_PASS0_CHUNKED : K_PASS0, s, [&] { return pass(0); }));
   HIP_TRY(timed(chunked ? K_PASS_CHUNKED : K_PASS, s, [&] {
-    for (int p = 1; p < kKeyDigits; ++p) {
+    for (int p = 1; p < passes; ++p) {
       const hipError_t e = pass(p);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
-  }, kKeyDigits - 1));
-  uint64_t *sorted = buf[(kKeyDigits - 1) & 1];  // == sort_b
+  }, passes - 1));
+  uint64_t *sorted = buf[(passes - 1) & 1];  // == sort_b (8 or 6 passes)
   // run-length encoding (+ rows and column items when statistics are wanted)
   uint64_t *lbs = ws.at<uint64_t>(L.lbs);
   uint64_t *items = nullptr, *rpos = nullptr, *rlink = nullptr;
@@ -432,6 +450,7 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
   r.nnz_out = o.nnz;
   r.lb = lbs;
   r.ticket = ws.ticket();
+  r.lim = N;
   HIP_TRY(timed(K_RLE, s, [&] { return launch_rle(sh.scan, r, rle_tiles, s); }));
   if (!want_stats) return NS_OK;
   // rows: packets = distance between row heads, fan-out = links between them
@@ -444,11 +463,13 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
   return NS_OK;
 }
 
-// The eight quantities of a sorted COO matrix.
+// The eight quantities of a sorted COO matrix. A matrix of 2^32 packets or
+// more (fewer than 2^32 links) takes the 64-bit run reductions.
 int enqueue_matrix_stats(Ws &ws, const Shapes &sh, const ns_matrix_t *m, uint64_t *stats,
                          hipStream_t s) {
   const Layout &L = ws.L;
   const uint64_t cap = m->capacity < m->packets ? m->capacity : m->packets;
+  const bool wide = m->packets > kMaxPackets32;
   uint64_t *seg = ws.at<uint64_t>(L.seg);
   uint64_t *t_run = ws.at<uint64_t>(L.t_run);
   uint64_t *link_off = ws.at<uint64_t>(L.link_off);
@@ -483,12 +504,15 @@ int enqueue_matrix_stats(Ws &ws, const Shapes &sh, const ns_matrix_t *m, uint64_
   r.items = items;
   r.lb = lbs;
   r.ticket = ws.ticket();
+  r.wide = wide;
+  r.lim = cap;
   HIP_TRY(timed(K_RUNS, s, [&] { return launch_runs(sh.scan, 0, r, run_tiles, s); }));
   // fan-out = run length, source packets = run sum
   HIP_TRY(timed(K_SEGMAX, s, [&] { return launch_segmax(hpos, hval, row_off, 1, cap, stats, 5, 4, s); }));
   // valid packets = value sentinel, read before the column pass reuses hpos/hval
   HIP_TRY(timed(K_FINAL, s, [&] { return launch_finalize_matrix(hval, row_off, nullptr, m->nnz, stats, s); }));
-  int rc = enqueue_columns(ws, sh, items, tmp, link_off, 1, cap, stats, s);
+  int rc = enqueue_columns(ws, sh, items, tmp, link_off, 1, cap, stats, s,
+                           wide ? m->counts : nullptr);
   if (rc) return rc;
   HIP_TRY(timed(K_FINAL, s, [&] { return launch_finalize_matrix(nullptr, nullptr, ws.at<uint64_t>(L.col_off), nullptr, stats, s); }));
   return NS_OK;
@@ -667,7 +691,9 @@ std::string batch_key(int dev, const BatchArgs &b, void *ws, uint64_t ws_bytes) 
            b.win ? (void *)b.win->keys : nullptr, b.win ? (void *)b.win->counts : nullptr,
            b.win ? (void *)b.win->nnz : nullptr, (void *)nullptr,
            (unsigned long long)(b.win ? b.win->capacity : 0), b.sh.sort.block, b.sh.sort.items,
-           b.sh.scan.items, (unsigned long long)b.sh.chunked_min, ws, (unsigned long long)ws_bytes);
+           b.sh.scan.items * 100 + b.sh.digit_bits,
+           (unsigned long long)b.sh.chunked_min, ws,
+           (unsigned long long)ws_bytes);
   return std::string(buf);
 }
 
@@ -783,6 +809,7 @@ const char *ns_error_string(int code) {
     case NS_ERR_HIP: return "HIP runtime error";
     case NS_ERR_UNDERFLOW: return "subtraction below zero";
     case NS_ERR_UNSUPPORTED: return "size beyond the supported range";
+    case NS_ERR_BOUNDS: return "an index outside its array (bounds-checked build)";
     default: return "unknown error";
   }
 }
@@ -823,8 +850,9 @@ int ns_build_matrix(const uint32_t *src, const uint32_t *dst, uint64_t n, ns_mat
 
 int ns_stats(const ns_matrix_t *m, ns_stats_t *out, void *ws, uint64_t ws_bytes, void *stream) {
   if (!m || !out || !m->keys || !m->counts || !m->nnz) return NS_ERR_INVALID_ARG;
-  if (m->packets > kMaxPackets32) return NS_ERR_UNSUPPORTED;
   const uint64_t cap = m->capacity < m->packets ? m->capacity : m->packets;
+  // 2^32 packets or more: column items carry 32-bit link indices
+  if (m->packets > kMaxPackets32 && cap > kMaxPackets32 + 1) return NS_ERR_UNSUPPORTED;
   Ws w;
   int rc = check_ws(ws, ws_bytes, cap, 1, &w);
   if (rc) return rc;
@@ -906,6 +934,23 @@ int ns_accumulate_noalloc(const ns_matrix_t *acc_in, const ns_matrix_t *win, int
                          static_cast<hipStream_t>(stream), true);
 }
 
+// True when [p, p + n) is page-locked host memory known to the runtime
+// (hipHostMalloc, or torch's pin_memory). A pointer the runtime does not know
+// (pageable memory) makes the query fail; its error is consumed here so that
+// it does not surface from a later call.
+static bool page_locked(const uint32_t *p, uint64_t n) {
+  const uint32_t *ends[2] = {p, p + (n - 1)};
+  for (const uint32_t *q : ends) {
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, q) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    if (attr.type != hipMemoryTypeHost) return false;
+  }
+  return true;
+}
+
 int ns_stream_workspace_size(uint64_t batch, uint64_t capacity, uint64_t *bytes) {
   if (!bytes || batch == 0) return NS_ERR_INVALID_ARG;
   *bytes = stream_plan(batch, capacity).total;
@@ -924,6 +969,10 @@ int ns_build_matrix_streamed(const uint32_t *src, const uint32_t *dst, uint64_t 
   if (!ws || reinterpret_cast<uintptr_t>(ws) % kAlign) return NS_ERR_WORKSPACE;
   const StreamLayout SL = stream_plan(batch, out->capacity);
   if (ws_bytes < SL.total) return NS_ERR_WORKSPACE;
+  // the packets must be page-locked host memory: an asynchronous copy of a
+  // large pageable range makes the runtime lock the existing pages in place,
+  // which hosts may refuse (and the failure then surfaces on the device)
+  if (n > 0 && !(page_locked(src, n) && page_locked(dst, n))) return NS_ERR_INVALID_ARG;
   uint8_t *base = static_cast<uint8_t *>(ws);
   Ws w;
   int rc = check_ws(base + SL.inner, ws_bytes - SL.inner, batch, 1, &w);
@@ -948,13 +997,19 @@ int ns_build_matrix_streamed(const uint32_t *src, const uint32_t *dst, uint64_t 
   auto agg = [&](uint64_t k) -> ns_matrix_t * { return ((nb - 1 - k) & 1) == 0 ? out : &am; };
   Shapes sh;
   resolve_tuning(nullptr, &sh);
-  hipEvent_t copied[2] = {nullptr, nullptr}, freed[2] = {nullptr, nullptr};
+  hipEvent_t copied[2] = {nullptr, nullptr}, freed[2] = {nullptr, nullptr}, entry = nullptr;
   int status = NS_OK;
   for (int b = 0; b < 2 && status == NS_OK; ++b) {
     if (hipEventCreateWithFlags(&copied[b], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&freed[b], hipEventDisableTiming) != hipSuccess)
       status = NS_ERR_HIP;
   }
+  // work enqueued earlier on `stream` (an earlier call's builds) may still read
+  // the staging buffers: the first copies wait for it
+  if (status == NS_OK && cs != s &&
+      (hipEventCreateWithFlags(&entry, hipEventDisableTiming) != hipSuccess ||
+       hipEventRecord(entry, s) != hipSuccess || hipStreamWaitEvent(cs, entry, 0) != hipSuccess))
+    status = NS_ERR_HIP;
   // sub-partition k goes to staging buffer k&1 once the build of k-2 has read it
   auto copy_in = [&](uint64_t k) -> int {
     const int b = (int)(k & 1);
@@ -1015,6 +1070,7 @@ int ns_build_matrix_streamed(const uint32_t *src, const uint32_t *dst, uint64_t 
     if (copied[b]) hipEventDestroy(copied[b]);
     if (freed[b]) hipEventDestroy(freed[b]);
   }
+  if (entry) hipEventDestroy(entry);
   if (status != NS_OK) return status;
   out->packets = n;
   return NS_OK;

@@ -9,6 +9,8 @@
 // (a waited-on tile always belongs to a running workgroup).
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "ns_device.h"
 #include "ns_launch.h"
 
@@ -22,10 +24,29 @@ constexpr int kHistBlock = NS_HIST_BLOCK;
 #ifndef NS_LB_DEPTH
 #define NS_LB_DEPTH 4  // look-back words in flight per thread and round trip
 #endif
+// Debug builds (NS_BOUNDS_CHECK=1) check the index of every scatter and gather
+// of the radix passes and run scans against its array's bound; an index
+// outside raises bit 3 of the device error word and the access is skipped.
+#ifndef NS_BOUNDS_CHECK
+#define NS_BOUNDS_CHECK 0
+#endif
 
 namespace ns {
 
-__device__ int g_status;  // bit 0: subtraction below zero; bit 1: a capacity (hash table, merge output) is exceeded; bit 2: an input breaks its stated order
+__device__ int g_status;  // bit 0: subtraction below zero; bit 1: a capacity (hash table, merge output) is exceeded; bit 2: an input breaks its stated order; bit 3: an index outside its array (debug builds)
+
+// true when i < n; in debug builds, otherwise raises bit 3 of the error word
+__device__ __forceinline__ bool in_bounds(uint64_t i, uint64_t n) {
+#if NS_BOUNDS_CHECK
+  if (i < n) return true;
+  atomicOr(&g_status, 8);
+  return false;
+#else
+  (void)i;
+  (void)n;
+  return true;
+#endif
+}
 
 // ---------------------------------------------------------------------------
 // small utilities
@@ -258,56 +279,61 @@ __device__ __forceinline__ void peer_bit(uint32_t d, uint32_t &plo, uint32_t &ph
   phi = __builtin_amdgcn_bitop3_b32(phi, (uint32_t)(m >> 32), e, 0x90);
 }
 
+// Peer search over digit bits Bit .. R-1 (see peer_bit).
+template <int Bit, int R>
+__device__ __forceinline__ void peer_bits(uint32_t d, uint32_t &plo, uint32_t &phi) {
+  if constexpr (Bit < R) {
+    peer_bit<Bit>(d, plo, phi);
+    peer_bits<Bit + 1, R>(d, plo, phi);
+  }
+}
+
 // Stable rank of each key among the wave's keys with the same digit, in
 // (item, lane) order = original order; wcnt[d] holds the wave's running count
 // of digit d. The peer mask (lanes holding the same digit) is the intersection
-// over the 8 digit bits of the ballot where this lane's bit is set and its
+// over the R digit bits of the ballot where this lane's bit is set and its
 // complement where it is clear. The lowest lane of each group of equal digits
 // updates the counter, so a hot digit costs one LDS update per wave, not per
-// lane. FULL: every lane holds a key; otherwise digit kBins marks a missing
-// key, which is left out of every peer mask and not ranked.
-template <int ITEMS, bool FULL>
+// lane. FULL: every lane holds a key; otherwise digit 2^R marks a missing
+// key, which is left out of every peer mask and not ranked. CT is the
+// counter type (a wave's count of one digit is at most 64 * ITEMS).
+template <int ITEMS, bool FULL, int R = 8, typename CT = uint32_t>
 __device__ __forceinline__ void wave_rank(const uint32_t (&dig)[ITEMS], uint32_t (&rank)[ITEMS],
-                                          uint32_t *wcnt) {
+                                          CT *wcnt) {
+  constexpr uint32_t B = 1u << R;
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     const uint32_t d = dig[k];
     uint32_t plo = ~0u, phi = ~0u;
     if (!FULL) {
-      const uint64_t vm = ballot64(d < kBins);
+      const uint64_t vm = ballot64(d < B);
       plo = (uint32_t)vm;
       phi = (uint32_t)(vm >> 32);
     }
-    peer_bit<0>(d, plo, phi);
-    peer_bit<1>(d, plo, phi);
-    peer_bit<2>(d, plo, phi);
-    peer_bit<3>(d, plo, phi);
-    peer_bit<4>(d, plo, phi);
-    peer_bit<5>(d, plo, phi);
-    peer_bit<6>(d, plo, phi);
-    peer_bit<7>(d, plo, phi);
+    peer_bits<0, R>(d, plo, phi);
     const uint64_t peers = ((uint64_t)phi << 32) | plo;
-    if (FULL || d < kBins) {
+    if (FULL || d < B) {
       const uint32_t below = count_below(peers);
       const uint32_t old = wcnt[d];
       rank[k] = old + below;
-      if (below == 0) wcnt[d] = old + (uint32_t)__popcll(peers);
+      if (below == 0) wcnt[d] = (CT)(old + (uint32_t)__popcll(peers));
     }
   }
 }
 
-// Digits of a wave-striped tile (kBins for positions at or past n) and their
+// Digits of a wave-striped tile (2^R for positions at or past n) and their
 // stable ranks within the wave.
-template <int ITEMS, bool FULL>
+template <int ITEMS, bool FULL, int R = 8, typename CT = uint32_t>
 __device__ __forceinline__ void rank_tile(const uint64_t (&key)[ITEMS], uint32_t shift, uint32_t n,
                                           uint32_t wbase, int lane, uint32_t (&dig)[ITEMS],
-                                          uint32_t (&rank)[ITEMS], uint32_t *wcnt) {
+                                          uint32_t (&rank)[ITEMS], CT *wcnt) {
+  constexpr uint32_t B = 1u << R;
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
-    const uint32_t d = (uint32_t)(key[k] >> shift) & 255u;
-    dig[k] = (FULL || wbase + k * kWave + lane < n) ? d : kBins;
+    const uint32_t d = (uint32_t)(key[k] >> shift) & (B - 1);
+    dig[k] = (FULL || wbase + k * kWave + lane < n) ? d : B;
   }
-  wave_rank<ITEMS, FULL>(dig, rank, wcnt);
+  wave_rank<ITEMS, FULL, R, CT>(dig, rank, wcnt);
 }
 
 // Tile positions from the per-wave digit counts, on all BLOCK threads between
@@ -346,14 +372,15 @@ __device__ __forceinline__ void tile_offsets(uint32_t (*s_wcnt)[kBins], uint32_t
 }
 
 // Keys into the tile's LDS buffer in digit order.
-template <int ITEMS, bool FULL>
+template <int ITEMS, bool FULL, int R = 8, typename CT = uint32_t>
 __device__ __forceinline__ void place_tile(const uint64_t (&key)[ITEMS], const uint32_t (&dig)[ITEMS],
-                                           const uint32_t (&rank)[ITEMS], const uint32_t *wpos,
+                                           const uint32_t (&rank)[ITEMS], const CT *wpos,
                                            uint64_t *s_keys) {
+  constexpr uint32_t B = 1u << R;
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     const uint32_t d = dig[k];
-    if (FULL || d < kBins) s_keys[wpos[d] + rank[k]] = key[k];
+    if (FULL || d < B) s_keys[wpos[d] + rank[k]] = key[k];
   }
 }
 
@@ -361,29 +388,33 @@ __device__ __forceinline__ void place_tile(const uint64_t (&key)[ITEMS], const u
 // out[s_gdel[d] + i] for the key at LDS position i with digit d. A full tile
 // goes in unrolled batches so that each batch's LDS reads are in flight
 // together; a partial tile loops.
-template <int BLOCK, int ITEMS>
+template <int BLOCK, int ITEMS, int R = 8>
 __device__ __forceinline__ void write_tile(const uint64_t *s_keys, const uint64_t *s_gdel,
-                                           uint32_t n, uint32_t shift, int tid, uint64_t *out) {
+                                           uint32_t n, uint32_t shift, int tid, uint64_t *out,
+                                           uint64_t lim) {
+  constexpr uint32_t M = (1u << R) - 1;
   if (n == (uint32_t)(BLOCK * ITEMS)) {
     // opaque copy of the thread index: keeps the compiler from hoisting one
     // 64-bit address per item out of the tile loop (registers it lacks)
     uint32_t tb = tid;
     asm volatile("" : "+v"(tb));
-    constexpr int R = ITEMS < 8 ? ITEMS : 8;
+    constexpr int U = ITEMS < 8 ? ITEMS : 8;  // keys per unrolled batch
 #pragma unroll
-    for (int q0 = 0; q0 < ITEMS; q0 += R) {
-      uint64_t x[R], g[R];
+    for (int q0 = 0; q0 < ITEMS; q0 += U) {
+      uint64_t x[U], g[U];
 #pragma unroll
-      for (int q = 0; q < R; ++q) x[q] = s_keys[tb + (q0 + q) * BLOCK];
+      for (int q = 0; q < U; ++q) x[q] = s_keys[tb + (q0 + q) * BLOCK];
 #pragma unroll
-      for (int q = 0; q < R; ++q) g[q] = s_gdel[(uint32_t)(x[q] >> shift) & 255u] + tb;
+      for (int q = 0; q < U; ++q) g[q] = s_gdel[(uint32_t)(x[q] >> shift) & M] + tb;
 #pragma unroll
-      for (int q = 0; q < R; ++q) out[g[q] + (q0 + q) * BLOCK] = x[q];
+      for (int q = 0; q < U; ++q)
+        if (in_bounds(g[q] + (q0 + q) * BLOCK, lim)) out[g[q] + (q0 + q) * BLOCK] = x[q];
     }
   } else {
     for (uint32_t i = tid; i < n; i += BLOCK) {
       const uint64_t x = s_keys[i];
-      out[s_gdel[(uint32_t)(x >> shift) & 255u] + i] = x;
+      const uint64_t g = s_gdel[(uint32_t)(x >> shift) & M] + i;
+      if (in_bounds(g, lim)) out[g] = x;
     }
   }
 }
@@ -434,14 +465,14 @@ __device__ __forceinline__ void pass_load(const PassArgs &a, uint64_t start, uin
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const uint64_t i = start + wbase + k * kWave + lane;
-      key[k] = PACKETS ? pack_key(a.src[i], a.dst[i]) : a.in[i];
+      key[k] = !in_bounds(i, a.lim) ? 0 : PACKETS ? pack_key(a.src[i], a.dst[i]) : a.in[i];
     }
   } else {
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const uint32_t li = wbase + k * kWave + lane;
       uint64_t x = 0;
-      if (li < n) {
+      if (li < n && in_bounds(start + li, a.lim)) {
         if (PACKETS) x = pack_key(a.src[start + li], a.dst[start + li]);
         else x = a.in[start + li];
       }
@@ -544,7 +575,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       a.lb_next[(uint64_t)t * kBins + tid] = 0;
     }
     __syncthreads();
-    write_tile<BLOCK, ITEMS>(s_keys, s_gdel, n, shift, tid, a.out);
+    write_tile<BLOCK, ITEMS>(s_keys, s_gdel, n, shift, tid, a.out, a.lim);
     if (!pipe && tid < kWave) {
       uint32_t nw = 0;
       const uint32_t tk = pass_ticket(a, layers, tickets, &nw);
@@ -598,37 +629,38 @@ __device__ __forceinline__ void chunk_geometry(const ChunkArgs &c, uint32_t tile
   *per = p ? p : 1;
 }
 
-template <int BLOCK, bool PACKETS>
+template <int BLOCK, bool PACKETS, int R>
 __global__ __launch_bounds__(BLOCK) void k_chunk_hist(PassArgs a, ChunkArgs c, uint32_t tile) {
   constexpr int C = 4;  // interleaved counter copies (see k_hist_packets)
-  __shared__ uint32_t s_h[kBins * C];
+  constexpr uint32_t B = 1u << R;
+  __shared__ uint32_t s_h[B * C];
   uint64_t lo, n, tiles, per;
   chunk_geometry(c, tile, &lo, &n, &tiles, &per);
   const uint32_t cp = threadIdx.x & (C - 1);
   for (uint32_t ch = blockIdx.x; ch < c.chunks; ch += gridDim.x) {
-    for (int i = threadIdx.x; i < kBins * C; i += BLOCK) s_h[i] = 0;
+    for (int i = threadIdx.x; i < (int)(B * C); i += BLOCK) s_h[i] = 0;
     __syncthreads();
     const uint64_t b = min(n, (uint64_t)ch * per * tile), e = min(n, b + per * tile);
-    constexpr int R = 8;
-    for (uint64_t i0 = lo + b + threadIdx.x; i0 < lo + e; i0 += (uint64_t)R * BLOCK) {
-      uint64_t k[R];
+    constexpr int U = 8;
+    for (uint64_t i0 = lo + b + threadIdx.x; i0 < lo + e; i0 += (uint64_t)U * BLOCK) {
+      uint64_t k[U];
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
+      for (int q = 0; q < U; ++q) {
         const uint64_t i = i0 + (uint64_t)q * BLOCK;
         k[q] = i < lo + e ? (PACKETS ? pack_key(a.src[i], a.dst[i]) : a.in[i]) : 0;
       }
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
+      for (int q = 0; q < U; ++q) {
         if (i0 + (uint64_t)q * BLOCK >= lo + e) break;
-        atomicAdd(&s_h[(((uint32_t)(k[q] >> a.shift)) & 255u) * C + cp], 1u);
+        atomicAdd(&s_h[(((uint32_t)(k[q] >> a.shift)) & (B - 1)) * C + cp], 1u);
       }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kBins; i += BLOCK) {
+    for (int i = threadIdx.x; i < (int)B; i += BLOCK) {
       uint32_t v = 0;
 #pragma unroll
       for (int q = 0; q < C; ++q) v += s_h[i * C + q];
-      c.count[(uint64_t)ch * kBins + i] = v;
+      c.count[(uint64_t)ch * B + i] = v;
     }
     __syncthreads();
   }
@@ -636,15 +668,17 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_hist(PassArgs a, ChunkArgs c, u
 
 // The chunk scan: prefix[ch][d] = keys with digit d in chunks before ch, and
 // total[d] = keys with digit d, in three coalesced steps over the row-major
-// count table (a row is the 256 counts of one chunk): each workgroup sums the
-// rows of one block of consecutive chunks, the block sums are scanned per
+// count table (a row is the c.bins counts of one chunk): each workgroup sums
+// the rows of one block of consecutive chunks, the block sums are scanned per
 // digit, and each block then writes its chunks' prefixes from its own start.
-// Thread d of every workgroup owns digit d, so each row is one 1 KiB read.
+// Thread x of a workgroup with blockIdx.y = g owns digit d = 256 g + x, so a
+// row is read in coalesced 1 KiB pieces.
 __global__ __launch_bounds__(256) void k_chunk_sums(ChunkArgs c, uint32_t rows) {
-  const uint32_t r0 = blockIdx.x * rows, r1 = min(c.chunks, r0 + rows), d = threadIdx.x;
+  const uint32_t r0 = blockIdx.x * rows, r1 = min(c.chunks, r0 + rows);
+  const uint32_t d = blockIdx.y * 256 + threadIdx.x;
   uint64_t s = 0;
-  for (uint32_t r = r0; r < r1; ++r) s += c.count[(uint64_t)r * kBins + d];
-  c.bsum[(uint64_t)blockIdx.x * kBins + d] = s;
+  for (uint32_t r = r0; r < r1; ++r) s += c.count[(uint64_t)r * c.bins + d];
+  c.bsum[(uint64_t)blockIdx.x * c.bins + d] = s;
 }
 
 // One workgroup per digit; thread i scans blocks [i*per, (i+1)*per).
@@ -659,7 +693,7 @@ __global__ __launch_bounds__(256) void k_chunk_bscan(ChunkArgs c, uint32_t block
 #pragma unroll
   for (int q = 0; q < kMaxPer; ++q) {
     const uint32_t b = b0 + q;
-    v[q] = (q < (int)per && b < blocks) ? c.bsum[(uint64_t)b * kBins + d] : 0;
+    v[q] = (q < (int)per && b < blocks) ? c.bsum[(uint64_t)b * c.bins + d] : 0;
     sum += v[q];
   }
   uint64_t tot;
@@ -667,18 +701,19 @@ __global__ __launch_bounds__(256) void k_chunk_bscan(ChunkArgs c, uint32_t block
 #pragma unroll
   for (int q = 0; q < kMaxPer; ++q) {
     const uint32_t b = b0 + q;
-    if (q < (int)per && b < blocks) c.bsum[(uint64_t)b * kBins + d] = run;
+    if (q < (int)per && b < blocks) c.bsum[(uint64_t)b * c.bins + d] = run;
     run += v[q];
   }
   if (threadIdx.x == 0) c.total[d] = tot;
 }
 
 __global__ __launch_bounds__(256) void k_chunk_prefix(ChunkArgs c, uint32_t rows) {
-  const uint32_t r0 = blockIdx.x * rows, r1 = min(c.chunks, r0 + rows), d = threadIdx.x;
-  uint64_t run = c.bsum[(uint64_t)blockIdx.x * kBins + d];
+  const uint32_t r0 = blockIdx.x * rows, r1 = min(c.chunks, r0 + rows);
+  const uint32_t d = blockIdx.y * 256 + threadIdx.x;
+  uint64_t run = c.bsum[(uint64_t)blockIdx.x * c.bins + d];
   for (uint32_t r = r0; r < r1; ++r) {
-    c.prefix[(uint64_t)r * kBins + d] = run;
-    run += c.count[(uint64_t)r * kBins + d];
+    c.prefix[(uint64_t)r * c.bins + d] = run;
+    run += c.count[(uint64_t)r * c.bins + d];
   }
 }
 
@@ -742,9 +777,126 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         n = (uint32_t)min((uint64_t)TILE, lo + nk - start);
         pass_load<ITEMS, PACKETS>(a, start, n, wbase, lane, TILE, key);
       }
-      write_tile<BLOCK, ITEMS>(s_keys, s_gdel, n_cur, shift, tid, a.out);
+      write_tile<BLOCK, ITEMS>(s_keys, s_gdel, n_cur, shift, tid, a.out, a.lim);
       __syncthreads();
       gbase += tot;
+    }
+    __syncthreads();
+  }
+}
+
+// The chunked pass on 11-bit digits (2048 bins): 64-bit keys sort in 6
+// passes instead of 8, 32-bit column keys in 3 instead of 4. The tile flow is
+// that of k_pass_chunked; what changes with 2048 digits:
+// * per-wave digit counters are 16-bit (a wave counts at most 64 * ITEMS keys
+//   of a digit, and tile positions stay below 2^16), so the counters of a
+//   512-thread tile take 32 KiB of LDS;
+// * each thread owns DPT = 2048 / BLOCK consecutive digits: it sums them over
+//   the waves, a block scan of the threads' sums gives the tile positions, and
+//   it keeps its digits' running output positions in registers.
+template <int BLOCK, int ITEMS>
+constexpr int wide_waves() {
+  // occupancy the LDS allows: keys + 16-bit counters + output deltas
+  return (160 * 1024) / (BLOCK * ITEMS * 8 + (BLOCK / kWave) * kMaxBins * 2 + kMaxBins * 8) *
+         (BLOCK / kWave) / 4;
+}
+
+template <int BLOCK, int ITEMS, bool PACKETS>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(wide_waves<BLOCK, ITEMS>())))
+void k_pass_chunked_wide(PassArgs a, ChunkArgs c) {
+  constexpr int R = kWideBits;
+  constexpr int B = 1 << R;
+  constexpr int TILE = BLOCK * ITEMS;
+  constexpr int NW = BLOCK / kWave;
+  constexpr int DPT = B / BLOCK;  // consecutive digits owned by each thread
+  static_assert(B % BLOCK == 0 && TILE < 65536, "16-bit tile positions");
+  __shared__ uint64_t s_keys[TILE];
+  __shared__ uint16_t s_wcnt[NW][B];
+  __shared__ uint64_t s_gdel[B];  // output position of digit d's keys minus their tile position
+  __shared__ uint64_t s_tmp[NW];
+  __shared__ uint32_t s_chunk;
+
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const uint32_t shift = a.shift;
+  const uint32_t wbase = wv * (kWave * ITEMS);
+  const uint32_t d0 = tid * DPT;
+  uint64_t lo, nk, tiles, per;
+  chunk_geometry(c, TILE, &lo, &nk, &tiles, &per);
+  uint64_t dbase[DPT];  // start of each owned digit's bucket
+  {
+    uint64_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+      dbase[j] = sum;
+      sum += c.total[d0 + j];
+    }
+    uint64_t tot;
+    const uint64_t x = block_excl_scan<BLOCK>(sum, s_tmp, &tot);
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) dbase[j] += lo + x;
+  }
+
+  for (;;) {
+    if (tid == 0) s_chunk = atomicAdd(a.ticket, 1u);
+    for (int i = tid; i < NW * B / 2; i += BLOCK) reinterpret_cast<uint32_t *>(&s_wcnt[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t ch = s_chunk;
+    if (ch >= c.chunks) break;
+    const uint64_t t0 = min(tiles, (uint64_t)ch * per), t1 = min(tiles, t0 + per);
+    uint64_t gbase[DPT];  // output position of the chunk's next key with each owned digit
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) gbase[j] = dbase[j] + c.prefix[(uint64_t)ch * B + d0 + j];
+    uint64_t key[ITEMS];
+    uint32_t n = 0;
+    if (t0 < t1) {
+      const uint64_t start = lo + t0 * TILE;
+      n = (uint32_t)min((uint64_t)TILE, lo + nk - start);
+      pass_load<ITEMS, PACKETS>(a, start, n, wbase, lane, TILE, key);
+    }
+    for (uint64_t t = t0; t < t1; ++t) {
+      uint32_t dig[ITEMS];
+      uint32_t rank[ITEMS];
+      const bool full = n == TILE;
+      if (full) rank_tile<ITEMS, true, R, uint16_t>(key, shift, n, wbase, lane, dig, rank, s_wcnt[wv]);
+      else rank_tile<ITEMS, false, R, uint16_t>(key, shift, n, wbase, lane, dig, rank, s_wcnt[wv]);
+      __syncthreads();
+      // tile positions: thread sums of its digits over the waves, block scan
+      uint32_t run[NW][DPT], tot[DPT];
+      uint32_t sum = 0;
+#pragma unroll
+      for (int j = 0; j < DPT; ++j) {
+        uint32_t r = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+          run[q][j] = r;
+          r += s_wcnt[q][d0 + j];
+        }
+        tot[j] = r;
+        sum += r;
+      }
+      uint64_t all;
+      uint32_t pos = (uint32_t)block_excl_scan<BLOCK>(sum, s_tmp, &all);
+#pragma unroll
+      for (int j = 0; j < DPT; ++j) {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) s_wcnt[q][d0 + j] = (uint16_t)(pos + run[q][j]);
+        s_gdel[d0 + j] = gbase[j] - pos;
+        gbase[j] += tot[j];
+        pos += tot[j];
+      }
+      __syncthreads();
+      if (full) place_tile<ITEMS, true, R, uint16_t>(key, dig, rank, s_wcnt[wv], s_keys);
+      else place_tile<ITEMS, false, R, uint16_t>(key, dig, rank, s_wcnt[wv], s_keys);
+      __syncthreads();
+      for (int i = tid; i < NW * B / 2; i += BLOCK) reinterpret_cast<uint32_t *>(&s_wcnt[0][0])[i] = 0;
+      const uint32_t n_cur = n;
+      if (t + 1 < t1) {  // the next tile's keys load while this one is written
+        const uint64_t start = lo + (t + 1) * TILE;
+        n = (uint32_t)min((uint64_t)TILE, lo + nk - start);
+        pass_load<ITEMS, PACKETS>(a, start, n, wbase, lane, TILE, key);
+      }
+      write_tile<BLOCK, ITEMS, R>(s_keys, s_gdel, n_cur, shift, tid, a.out, a.lim);
+      __syncthreads();
     }
     __syncthreads();
   }
@@ -841,7 +993,7 @@ __device__ __forceinline__ ScanTile scan_tile(const uint64_t *tile_off, const ui
 // which searches past the tile end; only inside the segment).
 template <int BLOCK, int ITEMS>
 __device__ __forceinline__ void scan_load(const uint64_t *keys, const ScanTile &g, uint64_t (&kr)[ITEMS],
-                                          uint64_t &kprev, uint64_t &knext) {
+                                          uint64_t &kprev, uint64_t &knext, uint64_t lim) {
   const int tid = threadIdx.x;
   // opaque copy of the thread index: keeps the compiler from hoisting one
   // 64-bit address per item out of the tile loop (registers it lacks)
@@ -851,10 +1003,11 @@ __device__ __forceinline__ void scan_load(const uint64_t *keys, const ScanTile &
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     const uint32_t i = tb + k * BLOCK;
-    kr[k] = i < g.n ? base[i] : 0;
+    kr[k] = i < g.n && in_bounds(g.start + i, lim) ? base[i] : 0;
   }
-  if (tid == 0 && g.n && g.start > g.seg_lo) kprev = keys[g.start - 1];
-  if (tid / kWave == 2 && g.n && g.start + g.n < g.seg_hi) knext = keys[g.start + g.n];
+  if (tid == 0 && g.n && g.start > g.seg_lo && in_bounds(g.start - 1, lim)) kprev = keys[g.start - 1];
+  if (tid / kWave == 2 && g.n && g.start + g.n < g.seg_hi && in_bounds(g.start + g.n, lim))
+    knext = keys[g.start + g.n];
 }
 
 // ---------------------------------------------------------------------------
@@ -904,7 +1057,7 @@ void k_rle(RleArgs a) {
   __syncthreads();
   ScanTile g = scan_tile(a.tile_off, a.seg_off, s_next, s_next_w, total, TILE);
   uint64_t kr[ITEMS], kprev = 0, knext = 0;
-  scan_load<BLOCK, ITEMS>(a.keys, g, kr, kprev, knext);
+  scan_load<BLOCK, ITEMS>(a.keys, g, kr, kprev, knext, a.lim);
 
   while (g.t < total) {
     const uint32_t t = g.t, w = g.w, first = g.first, n = g.n;
@@ -977,7 +1130,7 @@ void k_rle(RleArgs a) {
     __syncthreads();
     const uint64_t L0 = s_L0, R0 = s_R0, trail = s_trail;
     g = scan_tile(a.tile_off, a.seg_off, s_next, s_next_w, total, TILE);
-    scan_load<BLOCK, ITEMS>(a.keys, g, kr, kprev, knext);  // next tile, in flight below
+    scan_load<BLOCK, ITEMS>(a.keys, g, kr, kprev, knext, a.lim);  // next tile, in flight below
     // positional per-segment output: global link index at this segment's start,
     // published by the segment's first tile (an earlier ticket, so it arrives)
     if (a.win_keys && tid == 0) {
@@ -1009,7 +1162,7 @@ void k_rle(RleArgs a) {
           a.link_off[v] = Le;
           a.row_off[v] = Re;
         }
-        if (a.rpos) {
+        if (a.rpos && in_bounds(Re, a.lim + 2)) {
           a.rpos[Re] = a.seg_off[a.W];
           a.rlink[Re] = Le;
         }
@@ -1024,9 +1177,10 @@ void k_rle(RleArgs a) {
       const uint64_t e = (r + 1 < TL) ? start + s_hpos[r + 1] : trail;
       const uint64_t cnt = e - (start + p);
       const uint64_t L = L0 + r;
+      if (!in_bounds(L, a.lim)) continue;
       if (a.ukeys) a.ukeys[L] = K;
       if (a.counts) a.counts[L] = cnt;
-      if (a.win_keys) {
+      if (a.win_keys && in_bounds(wpos + r, a.lim)) {
         a.win_keys[wpos + r] = K;
         a.win_counts[wpos + r] = cnt;
       }
@@ -1034,6 +1188,7 @@ void k_rle(RleArgs a) {
     }
     if (a.rpos) {
       for (uint32_t q = tid; q < TR; q += BLOCK) {
+        if (!in_bounds(R0 + q, a.lim + 2)) continue;
         a.rpos[R0 + q] = start + s_rpos[q];
         a.rlink[R0 + q] = L0 + s_rlr[q];
       }
@@ -1052,17 +1207,23 @@ void k_rle(RleArgs a) {
 // head stores its position and the exclusive value prefix, so consecutive
 // heads give run length (fan-out / fan-in) and run sum (packets). Tiles come
 // one ahead as in k_rle.
+// WIDE (matrices of 2^32 packets or more, whose counts and run sums need 64
+// bits): values and their tile sums are 64-bit, a column item carries the
+// link's index in the matrix instead of its count (dst<<32 | link index, so
+// the matrix has fewer than 2^32 links), and the column runs read the count
+// of each item's link from `gather` (the matrix counts).
 // ---------------------------------------------------------------------------
-template <int ITEMS, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_waves<ITEMS, 5>())))
+template <int ITEMS, int MODE, bool WIDE = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_waves<ITEMS, WIDE ? 7 : 5>())))
 void k_runs(RunArgs a) {
   constexpr int BLOCK = 256;
   constexpr int TILE = BLOCK * ITEMS;
   static_assert(TILE <= 65536, "tile positions are 16-bit");
+  using V = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
   __shared__ uint64_t s_g[pd(TILE) + 1];  // s_g[pd(1 + i)]: group key (a 32-bit address; 2^32 marks "none")
-  __shared__ uint32_t s_v[pd(TILE)];      // s_v[pd(i)]: value (< 2^32)
+  __shared__ V s_v[pd(TILE)];             // s_v[pd(i)]: value (< 2^32 unless WIDE)
   __shared__ uint16_t s_hp[TILE];      // head local positions
-  __shared__ uint32_t s_hv[TILE];      // tile-local exclusive value prefix at head
+  __shared__ V s_hv[TILE];             // tile-local exclusive value prefix at head
   __shared__ uint64_t s_tmp[BLOCK / kWave];
   __shared__ uint64_t s_H0, s_V0;
   __shared__ uint32_t s_next, s_next_w;
@@ -1074,7 +1235,7 @@ void k_runs(RunArgs a) {
   ScanTile g = scan_tile(a.tile_off, a.seg_off, s_next, s_next_w, total, TILE);
   uint64_t kr[ITEMS], cr[ITEMS], kprev = 0, knext = 0;
   auto load = [&]() {
-    scan_load<BLOCK, ITEMS>(a.keys, g, kr, kprev, knext);
+    scan_load<BLOCK, ITEMS>(a.keys, g, kr, kprev, knext, a.lim);
     if (MODE == 0) {
       uint32_t tb = tid;
       asm volatile("" : "+v"(tb));
@@ -1082,7 +1243,7 @@ void k_runs(RunArgs a) {
 #pragma unroll
       for (int k = 0; k < ITEMS; ++k) {
         const uint32_t i = tb + k * BLOCK;
-        cr[k] = i < g.n ? base[i] : 0;
+        cr[k] = i < g.n && in_bounds(g.start + i, a.lim) ? base[i] : 0;
       }
     }
   };
@@ -1097,8 +1258,11 @@ void k_runs(RunArgs a) {
       if (i < n) {
         s_g[pd(1 + i)] = kr[k] >> 32;
         if (MODE == 0) {
-          s_v[pd(i)] = (uint32_t)cr[k];
-          if (a.items) a.items[start + i] = (kr[k] << 32) | cr[k];
+          s_v[pd(i)] = (V)cr[k];
+          if (a.items && in_bounds(start + i, a.lim))
+            a.items[start + i] = (kr[k] << 32) | (WIDE ? start + i : cr[k]);
+        } else if (WIDE) {
+          s_v[pd(i)] = in_bounds((uint32_t)kr[k], a.lim) ? a.gather[(uint32_t)kr[k]] : 0;
         } else {
           s_v[pd(i)] = (uint32_t)kr[k];
         }
@@ -1107,7 +1271,8 @@ void k_runs(RunArgs a) {
     if (tid == 0) s_g[pd(0)] = start > seg_lo ? (kprev >> 32) : ~0ull;
     __syncthreads();
 
-    uint32_t hmask = 0, vsum = 0;
+    uint32_t hmask = 0;
+    V vsum = 0;
     const uint32_t p0 = tid * ITEMS;
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
@@ -1117,12 +1282,25 @@ void k_runs(RunArgs a) {
         vsum += s_v[pd(p)];
       }
     }
-    uint64_t tot;
-    const uint64_t x = block_excl_scan<BLOCK>(((uint64_t)__popc(hmask) << 32) | vsum, s_tmp, &tot);
-    const uint32_t xv = (uint32_t)x, xh = (uint32_t)(x >> 32);
-    const uint32_t TV = (uint32_t)tot, TH = (uint32_t)(tot >> 32);
+    V xv, TV;
+    uint32_t xh, TH;
+    if constexpr (WIDE) {  // heads and 64-bit values in two scans
+      uint64_t th, tv;
+      xh = (uint32_t)block_excl_scan<BLOCK>(__popc(hmask), s_tmp, &th);
+      xv = block_excl_scan<BLOCK>(vsum, s_tmp, &tv);
+      TH = (uint32_t)th;
+      TV = tv;
+    } else {  // both in one 64-bit scan: heads in the high half, values in the low
+      uint64_t tot;
+      const uint64_t x = block_excl_scan<BLOCK>(((uint64_t)__popc(hmask) << 32) | vsum, s_tmp, &tot);
+      xv = (uint32_t)x;
+      xh = (uint32_t)(x >> 32);
+      TV = (uint32_t)tot;
+      TH = (uint32_t)(tot >> 32);
+    }
     {
-      uint32_t jh = xh, run = xv;
+      uint32_t jh = xh;
+      V run = xv;
 #pragma unroll
       for (int k = 0; k < ITEMS; ++k) {
         const uint32_t p = p0 + k;
@@ -1161,11 +1339,14 @@ void k_runs(RunArgs a) {
       if (t == total - 1) {
         const uint64_t He = H0 + TH;
         for (uint32_t v = w + 1; v <= a.W; ++v) a.head_off[v] = He;
-        a.hpos[He] = a.seg_off[a.W];
-        a.hval[He] = V0 + TV;
+        if (in_bounds(He, a.lim + 2)) {
+          a.hpos[He] = a.seg_off[a.W];
+          a.hval[He] = V0 + TV;
+        }
       }
     }
     for (uint32_t h = tid; h < TH; h += BLOCK) {
+      if (!in_bounds(H0 + h, a.lim + 2)) continue;
       a.hpos[H0 + h] = start + s_hp[h];
       a.hval[H0 + h] = V0 + s_hv[h];
     }
@@ -1701,40 +1882,56 @@ hipError_t launch_pass(const SortShape &sh, const PassArgs &a, uint64_t max_tile
   return hipErrorInvalidValue;
 }
 
-template <int B, int I, bool P>
+template <int B, int I, bool P, int BITS>
 static hipError_t pass_chunked_impl(const PassArgs &a, ChunkArgs c, uint64_t max_keys,
                                     int count_kind, hipStream_t s) {
   static uint64_t cap[64], hcap[64];
   const int d = device_id();
-  if (!cap[d]) cap[d] = resident(k_pass_chunked<B, I, P>, B);
-  if (!hcap[d]) hcap[d] = resident(k_chunk_hist<256, P>, 256);
+  if (!cap[d]) {
+    if constexpr (BITS == 8) cap[d] = resident(k_pass_chunked<B, I, P>, B);
+    else cap[d] = resident(k_pass_chunked_wide<B, I, P>, B);
+  }
+  if (!hcap[d]) hcap[d] = resident(k_chunk_hist<256, P, BITS>, 256);
   // short chunks of kChunkTiles tiles, taken in order by the resident
   // workgroups: the chunks in flight at any time are neighbours, so each
   // digit's writes land in one narrow band of its bucket
   uint64_t ch = chunk_rows(max_keys, (uint64_t)B * I);
   if (ch > c.max_chunks) ch = c.max_chunks;
   c.chunks = (uint32_t)ch;
+  c.bins = 1u << BITS;
   const uint32_t blocks = (uint32_t)(ch < kChunkBlocks ? ch : kChunkBlocks);
   const uint32_t rows = (uint32_t)((ch + blocks - 1) / blocks);
   const uint32_t nb = (uint32_t)((ch + rows - 1) / rows);
   const int kind = tl_timing_kind;
   if (kind >= 0) tl_timing_kind = count_kind;
-  NS_LAUNCH((k_chunk_hist<256, P>), dim3(clamp_grid(ch, hcap[d])), dim3(256), s, a, c, (uint32_t)(B * I));
-  NS_LAUNCH(k_chunk_sums, dim3(nb), dim3(256), s, c, rows);
-  NS_LAUNCH(k_chunk_bscan, dim3(kBins), dim3(256), s, c, nb);
-  NS_LAUNCH(k_chunk_prefix, dim3(nb), dim3(256), s, c, rows);
+  NS_LAUNCH((k_chunk_hist<256, P, BITS>), dim3(clamp_grid(ch, hcap[d])), dim3(256), s, a, c, (uint32_t)(B * I));
+  NS_LAUNCH(k_chunk_sums, dim3(nb, c.bins / 256), dim3(256), s, c, rows);
+  NS_LAUNCH(k_chunk_bscan, dim3(c.bins), dim3(256), s, c, nb);
+  NS_LAUNCH(k_chunk_prefix, dim3(nb, c.bins / 256), dim3(256), s, c, rows);
   tl_timing_kind = kind;
-  NS_LAUNCH((k_pass_chunked<B, I, P>), dim3(clamp_grid(ch, cap[d])), dim3(B), s, a, c);
+  if constexpr (BITS == 8) {
+    NS_LAUNCH((k_pass_chunked<B, I, P>), dim3(clamp_grid(ch, cap[d])), dim3(B), s, a, c);
+  } else {
+    NS_LAUNCH((k_pass_chunked_wide<B, I, P>), dim3(clamp_grid(ch, cap[d])), dim3(B), s, a, c);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_pass_chunked(const SortShape &sh, const PassArgs &a, const ChunkArgs &c,
-                               uint64_t max_keys, int count_kind, hipStream_t s) {
+template <int BITS>
+static hipError_t pass_chunked_bits(const SortShape &sh, const PassArgs &a, const ChunkArgs &c,
+                                    uint64_t max_keys, int count_kind, hipStream_t s) {
   const bool P = a.src != nullptr;
-  if (sh.block == 256 && sh.items == 8) return P ? pass_chunked_impl<256, 8, true>(a, c, max_keys, count_kind, s) : pass_chunked_impl<256, 8, false>(a, c, max_keys, count_kind, s);
-  if (sh.block == 256 && sh.items == 16) return P ? pass_chunked_impl<256, 16, true>(a, c, max_keys, count_kind, s) : pass_chunked_impl<256, 16, false>(a, c, max_keys, count_kind, s);
-  if (sh.block == 512 && sh.items == 8) return P ? pass_chunked_impl<512, 8, true>(a, c, max_keys, count_kind, s) : pass_chunked_impl<512, 8, false>(a, c, max_keys, count_kind, s);
-  if (sh.block == 512 && sh.items == 16) return P ? pass_chunked_impl<512, 16, true>(a, c, max_keys, count_kind, s) : pass_chunked_impl<512, 16, false>(a, c, max_keys, count_kind, s);
+  if (sh.block == 256 && sh.items == 8) return P ? pass_chunked_impl<256, 8, true, BITS>(a, c, max_keys, count_kind, s) : pass_chunked_impl<256, 8, false, BITS>(a, c, max_keys, count_kind, s);
+  if (sh.block == 256 && sh.items == 16) return P ? pass_chunked_impl<256, 16, true, BITS>(a, c, max_keys, count_kind, s) : pass_chunked_impl<256, 16, false, BITS>(a, c, max_keys, count_kind, s);
+  if (sh.block == 512 && sh.items == 8) return P ? pass_chunked_impl<512, 8, true, BITS>(a, c, max_keys, count_kind, s) : pass_chunked_impl<512, 8, false, BITS>(a, c, max_keys, count_kind, s);
+  if (sh.block == 512 && sh.items == 16) return P ? pass_chunked_impl<512, 16, true, BITS>(a, c, max_keys, count_kind, s) : pass_chunked_impl<512, 16, false, BITS>(a, c, max_keys, count_kind, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_pass_chunked(const SortShape &sh, const PassArgs &a, const ChunkArgs &c,
+                               uint64_t max_keys, int bits, int count_kind, hipStream_t s) {
+  if (bits == 8) return pass_chunked_bits<8>(sh, a, c, max_keys, count_kind, s);
+  if (bits == kWideBits) return pass_chunked_bits<kWideBits>(sh, a, c, max_keys, count_kind, s);
   return hipErrorInvalidValue;
 }
 
@@ -1754,17 +1951,19 @@ hipError_t launch_rle(const ScanShape &sh, const RleArgs &a, uint64_t max_tiles,
   return hipErrorInvalidValue;
 }
 
-template <int I, int M>
+template <int I, int M, bool WIDE = false>
 static hipError_t runs_impl(const RunArgs &a, uint64_t max_tiles, hipStream_t s) {
   static uint64_t cap[64];
   const int d = device_id();
-  if (!cap[d]) cap[d] = resident(k_runs<I, M>, 256);
-  NS_LAUNCH((k_runs<I, M>), dim3(clamp_grid(max_tiles, cap[d])), dim3(256), s, a);
+  if (!cap[d]) cap[d] = resident(k_runs<I, M, WIDE>, 256);
+  NS_LAUNCH((k_runs<I, M, WIDE>), dim3(clamp_grid(max_tiles, cap[d])), dim3(256), s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_runs(const ScanShape &sh, int mode, const RunArgs &a, uint64_t max_tiles,
                        hipStream_t s) {
+  if (a.wide)  // matrices of 2^32 packets or more: one tile shape (256 x 8)
+    return mode == 0 ? runs_impl<8, 0, true>(a, max_tiles, s) : runs_impl<8, 1, true>(a, max_tiles, s);
   if (sh.items == 4) return mode == 0 ? runs_impl<4, 0>(a, max_tiles, s) : runs_impl<4, 1>(a, max_tiles, s);
   if (sh.items == 8) return mode == 0 ? runs_impl<8, 0>(a, max_tiles, s) : runs_impl<8, 1>(a, max_tiles, s);
   if (sh.items == 16) return mode == 0 ? runs_impl<16, 0>(a, max_tiles, s) : runs_impl<16, 1>(a, max_tiles, s);
@@ -1828,7 +2027,7 @@ hipError_t read_and_clear_status(int *host_status) {
   if (e != hipSuccess) return e;
   const int zero = 0;
   e = hipMemcpyToSymbol(HIP_SYMBOL(g_status), &zero, sizeof(int), 0, hipMemcpyHostToDevice);
-  *host_status = (v & 1) ? -5 : (v & 2) ? -2 : (v & 4) ? -1 : 0;
+  *host_status = (v & 8) ? -7 : (v & 1) ? -5 : (v & 2) ? -2 : (v & 4) ? -1 : 0;
   return e;
 }
 

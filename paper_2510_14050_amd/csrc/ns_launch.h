@@ -18,7 +18,7 @@ struct SortShape {
 };
 
 struct ScanShape {
-  int items;  // 4 or 8 (block is 256)
+  int items;  // 4, 8 or 16 positions per thread (block is 256)
   int tile() const { return 256 * items; }
 };
 
@@ -77,6 +77,7 @@ struct PassArgs {
   uint64_t *lb;              // look-back words of this pass [tiles][256]
   uint64_t *lb_next;         // cleared for the next pass
   uint32_t *ticket;
+  uint64_t lim;              // entries of the input and output arrays (bounds checks)
 };
 hipError_t launch_pass(const SortShape &sh, const PassArgs &a, uint64_t max_tiles, hipStream_t s);
 
@@ -91,20 +92,26 @@ inline uint64_t chunk_rows(uint64_t n, uint64_t tile) {
   const uint64_t r = (n + tile * kChunkTiles - 1) / (tile * kChunkTiles);
   return r ? r : 1;
 }
+// Digit widths of the chunked passes: byte digits, or 11-bit digits (2048
+// bins) that sort 64-bit keys in 6 passes and 32-bit column keys in 3.
+constexpr int kWideBits = 11;
+constexpr int kMaxBins = 1 << kWideBits;
 struct ChunkArgs {
   const uint64_t *seg_off;  // [2]: the segment is [seg_off[0], seg_off[1])
   uint32_t chunks;          // set by the launcher (<= max_chunks)
   uint32_t max_chunks;      // rows of count and prefix
-  uint32_t *count;          // [max_chunks][256] digit counts per chunk
-  uint64_t *prefix;         // [max_chunks][256] keys of the digit in earlier chunks
-  uint64_t *bsum;           // [kChunkBlocks][256] per row block: sum, then exclusive prefix
-  uint64_t *total;          // [256] keys per digit
+  uint32_t bins;            // set by the launcher: 2^(digit bits), the row length
+  uint32_t *count;          // [max_chunks][bins] digit counts per chunk
+  uint64_t *prefix;         // [max_chunks][bins] keys of the digit in earlier chunks
+  uint64_t *bsum;           // [blocks][bins] per row block: sum, then exclusive prefix
+  uint64_t *total;          // [bins] keys per digit
 };
-// Sorts at most max_keys keys. a.seg_off / tile_off / W / base / lb are unused;
-// a.ticket must start at zero. When kernel timing is on, the counting and
-// scan kernels are recorded under count_kind.
+// Sorts at most max_keys keys on the digit of `bits` bits (8 or kWideBits) at
+// a.shift. a.seg_off / tile_off / W / base / lb are unused; a.ticket must
+// start at zero. When kernel timing is on, the counting and scan kernels are
+// recorded under count_kind.
 hipError_t launch_pass_chunked(const SortShape &sh, const PassArgs &a, const ChunkArgs &c,
-                               uint64_t max_keys, int count_kind, hipStream_t s);
+                               uint64_t max_keys, int bits, int count_kind, hipStream_t s);
 
 // --- run-length encoding of sorted packet keys ------------------------------------
 struct RleArgs {
@@ -126,13 +133,17 @@ struct RleArgs {
   uint64_t *nnz_out;   // nullable: total links
   uint64_t *lb;        // [tiles][2]
   uint32_t *ticket;
+  uint64_t lim;        // positions (and so links) of the input; head arrays hold lim + 2
 };
 hipError_t launch_rle(const ScanShape &sh, const RleArgs &a, uint64_t max_tiles, hipStream_t s);
 
 // --- run reduction over a sorted array with explicit values -----------------------
 // mode 0: rows of a matrix (group = key>>32, value = counts[p]); also emits
 //         column items.
-// mode 1: columns of sorted items (group = item>>32, value = item & 0xffffffff).
+// mode 1: columns of sorted items (group = item>>32, value = item & 0xffffffff,
+//         or with `wide`, gather[item & 0xffffffff]).
+// wide: 64-bit values (matrices of 2^32 packets or more): column items carry
+//       the link index instead of the count, and tile sums are 64-bit.
 struct RunArgs {
   const uint64_t *keys;
   const uint64_t *counts;    // mode 0
@@ -145,6 +156,9 @@ struct RunArgs {
   uint64_t *items;           // mode 0, nullable
   uint64_t *lb;              // [tiles][2]
   uint32_t *ticket;
+  uint32_t wide;             // 0 or 1 (see above)
+  const uint64_t *gather;    // mode 1 with wide: the matrix counts
+  uint64_t lim;              // entries of keys / items / gather; head arrays hold lim + 2
 };
 hipError_t launch_runs(const ScanShape &sh, int mode, const RunArgs &a, uint64_t max_tiles,
                        hipStream_t s);
@@ -220,7 +234,8 @@ hipError_t launch_roll_update(const RollTables &t, const RollDelta &d, uint64_t 
 hipError_t launch_roll_stats(const RollTables &t, uint64_t *out, hipStream_t s);
 hipError_t launch_roll_compact(const RollTables &from, const RollTables &to, hipStream_t s);
 
-// device error word: bit 0 underflow, bit 1 capacity (hash table full)
+// device error word: bit 0 underflow, bit 1 capacity (hash table full), bit 2
+// invalid input, bit 3 an index outside its array (bounds-checked builds)
 hipError_t read_and_clear_status(int *host_status);
 
 // Kernel timing: while tl_timing_kind >= 0, every launch on this thread takes

@@ -17,6 +17,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libns.so")
+# the same library with every scatter / gather index of the radix passes and
+# run scans checked against its bound (a violation raises NS_ERR_BOUNDS)
+DEBUG_LIB_PATH = os.path.join(HERE, "libns_debug.so")
 
 STAT_NAMES = (
     "valid_packets", "unique_links", "unique_sources", "unique_destinations",
@@ -27,7 +30,7 @@ STAT_NAMES = (
 NS_OK = 0
 ERRORS = {
     -1: "NS_ERR_INVALID_ARG", -2: "NS_ERR_CAPACITY", -3: "NS_ERR_WORKSPACE",
-    -4: "NS_ERR_HIP", -5: "NS_ERR_UNDERFLOW", -6: "NS_ERR_UNSUPPORTED",
+    -4: "NS_ERR_HIP", -5: "NS_ERR_UNDERFLOW", -6: "NS_ERR_UNSUPPORTED", -7: "NS_ERR_BOUNDS",
 }
 
 
@@ -261,11 +264,16 @@ class StreamWorkspace:
 def build_matrix_streamed(src, dst, out: Matrix, ws: StreamWorkspace, stream=None,
                           copy_stream=None) -> Matrix:
     """ns_build_matrix_streamed: the matrix of host-resident packets (int32 CPU
-    tensors, pinned for overlap), built in sub-partitions of ws.batch packets."""
+    tensors in page-locked memory, e.g. torch.empty(..., pin_memory=True)),
+    built in sub-partitions of ws.batch packets. Pageable tensors are refused
+    (the library would reject them too)."""
     torch = _torch()
     for x in (src, dst):
         assert x.dtype == torch.int32 and not x.is_cuda and x.is_contiguous(), \
             "int32 host contiguous"
+        if x.numel() and not x.is_pinned():
+            raise ValueError("ns_build_matrix_streamed needs page-locked host memory "
+                             "(pin_memory=True)")
     n = src.numel()
     assert dst.numel() == n
     v = out.view()

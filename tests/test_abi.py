@@ -89,14 +89,18 @@ def test_host_argument_errors(lib):
                              need.value - 1, None) == -3
     assert lib.ns_accumulate(ctypes.byref(a), ctypes.byref(b), 1, ctypes.byref(c),
                              ctypes.c_void_p((1 << 20) + 8), 1 << 40, None) == -3
-    # stats of a matrix holding 2^32 packets or more is out of range
-    huge = ns.MatrixView(1024, 2048, 3072, 100, 1 << 32)
+    # stats of a matrix holding 2^32 packets or more need fewer than 2^32 + 1 entries
+    huge = ns.MatrixView(1024, 2048, 3072, (1 << 32) + 2, 1 << 33)
     assert lib.ns_stats(ctypes.byref(huge), ctypes.c_void_p(256), ws, 1 << 40, None) == -6
     # batch: bad tuning, capacity
     t = ns.tuning(sort_block=128)
     off = ctypes.c_void_p(256)
     assert lib.ns_batch_stats(off, off, off, 1, 10, off, None, None, None, ctypes.byref(t), ws,
                               1 << 40, None) == -1
+    for bits in (1, 4, 7, 9, 10, 12, 16):  # digit widths other than 8 and 11
+        t = ns.tuning(digit_bits=bits)
+        assert lib.ns_batch_stats(off, off, off, 1, 10, off, None, None, None, ctypes.byref(t),
+                                  ws, 1 << 40, None) == -1
     aggm = ns.MatrixView(1024, 2048, 3072, 9, 0)
     assert lib.ns_batch_stats(off, off, off, 1, 10, off, ctypes.byref(aggm), None, None, None, ws,
                               1 << 40, None) == -2

@@ -163,14 +163,31 @@ def test_batch_all_empty_and_single(gpu):
     check_batch(ns, one, one ^ np.uint32(1), *res)
 
 
-@pytest.mark.parametrize("shape", [(256, 8, 4), (256, 16, 8), (512, 8, 8), (512, 16, 4)])
+@pytest.mark.parametrize("shape", [(256, 8, 4), (256, 16, 8), (512, 8, 8), (512, 16, 4),
+                                   (512, 16, 16)])
 def test_batch_tuning_shapes(gpu, shape):
+    """Radix tiles and run tiles on ragged windows with their aggregate and
+    window matrices."""
     torch, ns = gpu
     say("batch tuning", shape)
     sizes = [9000, 1, 0, 40000, 33333, 2 * 8192 + 3]
     src, dst = zipf_packets(91, sum(sizes), pool=3000)
     t = ns.tuning(sort_block=shape[0], sort_items=shape[1], digit_bits=8, scan_items=shape[2])
     res = run_batch(torch, ns, src, dst, sizes, tune=t)
+    check_batch(ns, src, dst, *res)
+
+
+@pytest.mark.parametrize("scan", [4, 8, 16])
+@pytest.mark.parametrize("n", [8191, 8192, 8193, 65536 * 3 + 5, 1_000_003])
+def test_run_length_tiles_single_segment(gpu, n, scan):
+    """The run-length pass on one long segment (the aggregate alone) for each
+    run tile, around the tile sizes; long runs of equal keys cross tile ends
+    (a pool of 40 addresses)."""
+    torch, ns = gpu
+    say("run-length tiles", n, scan)
+    src, dst = zipf_packets(700 + n % 13, n, pool=40)
+    t = ns.tuning(scan_items=scan)
+    res = run_batch(torch, ns, src, dst, [n], tune=t, win=False, windows=False)
     check_batch(ns, src, dst, *res)
 
 
@@ -235,28 +252,44 @@ CHUNKED_CASES = {
 }
 
 
+@pytest.mark.parametrize("bits", [8, 11])
 @pytest.mark.parametrize("shape", [(256, 8), (256, 16), (512, 8), (512, 16)])
 @pytest.mark.parametrize("case", list(CHUNKED_CASES))
-def test_batch_chunked_single_segment(gpu, case, shape):
+def test_batch_chunked_single_segment(gpu, case, shape, bits):
     """Single segments (the aggregate, or a batch of one window) forced onto
-    the chunked passes: same results as the oracle."""
+    the chunked passes, with byte digits and with 11-bit digits (6 key passes,
+    3 column passes): same results as the oracle."""
     torch, ns = gpu
     sizes = CHUNKED_CASES[case]
-    say("chunked single segment", case, shape)
+    say("chunked single segment", case, shape, "digit bits", bits)
     src, dst = zipf_packets(31 + len(sizes), sum(sizes), pool=2500)
-    t = ns.tuning(sort_block=shape[0], sort_items=shape[1], chunked_min=1)
+    t = ns.tuning(sort_block=shape[0], sort_items=shape[1], chunked_min=1, digit_bits=bits)
     for graph in (True, False):
         res = run_batch(torch, ns, src, dst, sizes, tune=t, graph=graph)
         check_batch(ns, src, dst, *res)
 
 
+@pytest.mark.parametrize("bits", [8, 11])
 @pytest.mark.parametrize("name", ["hot_link", "extremes", "scanner", "identical"])
-def test_batch_chunked_patterns(gpu, name):
+def test_batch_chunked_patterns(gpu, name, bits):
     torch, ns = gpu
     src, dst = {p[0]: p[1:] for p in patterns()}[name]
-    say("chunked pattern", name)
-    t = ns.tuning(chunked_min=1)
+    say("chunked pattern", name, "digit bits", bits)
+    t = ns.tuning(chunked_min=1, digit_bits=bits)
     res = run_batch(torch, ns, src, dst, [src.size], tune=t)
+    check_batch(ns, src, dst, *res)
+
+
+@pytest.mark.parametrize("n", [2047, 2048, 2049, 8191, 8193, 32767, 32769, 100_003])
+def test_wide_digits_tile_and_chunk_edges(gpu, n):
+    """11-bit digits around the digit count (2048), the tile (8192 keys) and
+    the chunk (4 tiles): one segment on the chunked passes, through the
+    aggregate-only call, against the oracle."""
+    torch, ns = gpu
+    say("wide digits, n =", n)
+    src, dst = zipf_packets(4000 + n % 97, n, pool=3000, s=1.1)
+    t = ns.tuning(chunked_min=1, digit_bits=11)
+    res = run_batch(torch, ns, src, dst, [n], tune=t, win=False, windows=False)
     check_batch(ns, src, dst, *res)
 
 
@@ -419,14 +452,17 @@ def test_workload_uneven1024(gpu):
     check_batch(ns, src, dst, *res)
 
 
-def test_workload_uneven1024_with_aggregate(gpu):
+@pytest.mark.parametrize("bits", [8, 11])
+def test_workload_uneven1024_with_aggregate(gpu, bits):
     """1024 uneven windows with their aggregate: the aggregate's 3.5 x 10^7 keys
     take the chunked passes with more chunks than chunk-scan blocks (several
-    chunk rows per block); matrix and statistics against the oracle."""
+    chunk rows per block), with byte and with 11-bit digits; matrix and
+    statistics against the oracle."""
     torch, ns = gpu
-    say("workload uneven1024 + aggregate")
+    say("workload uneven1024 + aggregate, digit bits", bits)
     wl = synth.uneven1024()
     src, dst = wl.concat()
     assert src.size >= (1 << 24) and src.size > 1024 * 4 * 8192  # chunked, > 1024 chunks
-    res = run_batch(torch, ns, src, dst, list(wl.sizes), agg=True, win=False)
+    res = run_batch(torch, ns, src, dst, list(wl.sizes), agg=True, win=False,
+                    tune=ns.tuning(digit_bits=bits, chunked_min=1 << 24))
     check_batch(ns, src, dst, *res)

@@ -122,3 +122,27 @@ def test_streamed_workload_size(gpu):
     assert ns.device_status() == 0
     k, c = out.numpy()
     assert np.array_equal(k, ok) and np.array_equal(c, oc)
+
+
+@pytest.mark.parametrize("batch", [1 << 18, 300_007])
+def test_streamed_calls_back_to_back_share_a_workspace(gpu, batch):
+    """Four calls issued without synchronising, on one workspace and one copy
+    stream, each from other packets into its own output: a call's first copies
+    wait for the builds the previous call left on the stream, so every output
+    equals the oracle's matrix of its own packets and nothing overflows."""
+    torch, ns = gpu
+    n = 1_200_011
+    say("streamed back to back, batch", batch)
+    ws = ns.StreamWorkspace(batch, n)
+    cs = torch.cuda.Stream()
+    inputs = [packets(300 + i, n - 7919 * i, pool=50_000 * (i + 1)) for i in range(4)]
+    hosts = [(host32(torch, s), host32(torch, d)) for s, d in inputs]
+    outs = [ns.Matrix(n) for _ in inputs]
+    for (hs, hd), out in zip(hosts, outs):
+        ns.build_matrix_streamed(hs, hd, out, ws, copy_stream=cs)
+    torch.cuda.synchronize()
+    assert ns.device_status() == 0
+    for (s, d), out in zip(inputs, outs):
+        ok, oc = oracle.build_matrix(s, d)
+        k, c = out.numpy()
+        assert np.array_equal(k, ok) and np.array_equal(c, oc)
