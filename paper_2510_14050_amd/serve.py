@@ -265,7 +265,9 @@ class Server:
         the slots possibly occupied in a table (live entries at the last
         compaction plus one per packet added since) could pass 60% of it. Live
         entries are bounded by the counts of the latest arrival already on the
-        host plus one per packet added after it, and by the packets in the ring."""
+        host plus one per packet added after it, and by the packets in the ring;
+        when that bound exceeds half a table, the exact counts of this update
+        are read (one synchronisation) before the state is declared too small."""
         n = int(st.sizes[seq])
         st.occ = [o + n for o in st.occ]
         caps = (self.link_slots, self.address_slots, self.address_slots)
@@ -276,7 +278,15 @@ class Server:
         in_ring = int(st.csum[seq + 1] - st.csum[max(0, seq + 1 - self.ring)])
         live = [min(k + added, in_ring) for k in known]
         if any(lv > 0.5 * c for lv, c in zip(live, caps)):
-            raise RuntimeError("rolling aggregate outgrows its hash tables; raise the slot counts")
+            # the bound is loose when the host has not seen a recent result:
+            # wait for this update and take its exact counts
+            self.s_roll.synchronize()
+            rs = self.roll_dev[seq % self.slots].cpu()
+            live = [int(rs[1]), int(rs[2]), int(rs[3])]
+            st.known = (seq, tuple(live))
+            if any(lv > 0.5 * c for lv, c in zip(live, caps)):
+                raise RuntimeError("rolling aggregate outgrows its hash tables; "
+                                   "raise the slot counts")
         nxt = 1 - st.si
         ns.rolling_compact(self.states[st.si], self.states[nxt])
         st.si = nxt
@@ -347,7 +357,8 @@ class Server:
                                       self.roll_host[k].numpy().view(np.uint64).copy(),
                                       t_arr, t, bidx)
                 rs = results[seq].rolling_stats
-                st.known = (seq, (int(rs[1]), int(rs[2]), int(rs[3])))
+                if seq > st.known[0]:
+                    st.known = (seq, (int(rs[1]), int(rs[2]), int(rs[3])))
                 done_q.popleft()
                 completed[0] += 1
 

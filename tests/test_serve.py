@@ -65,6 +65,66 @@ def small_windows(n_windows, seed=5, lo=8, hi=12):
     return [wl.window(w) for w in range(n_windows)]
 
 
+class _Stream:
+    def __init__(self):
+        self.syncs = 0
+
+    def synchronize(self):
+        self.syncs += 1
+
+
+def _compaction_setup(monkeypatch, exact, known, sizes):
+    """A rolling state's host bookkeeping with the device parts stubbed on the
+    CPU: 1000 link slots and 1000 address slots, a ring of 64 arrivals."""
+    import types
+
+    import torch
+
+    from paper_2510_14050_amd import serve
+    calls = []
+    monkeypatch.setattr(serve.ns, "rolling_compact", lambda a, b: calls.append((a, b)))
+    srv = types.SimpleNamespace(link_slots=1000, address_slots=1000, ring=64, slots=8,
+                                s_roll=_Stream(), states=["state0", "state1"],
+                                roll_dev=torch.zeros((8, 8), dtype=torch.int64))
+    st = types.SimpleNamespace(si=0, compactions=0, occ=[590, 590, 590], known=known,
+                               sizes=np.array(sizes, np.int64))
+    st.csum = np.concatenate([[0], np.cumsum(st.sizes)])
+    seq = len(sizes) - 1
+    srv.roll_dev[seq % 8, 1:4] = torch.tensor(exact)
+    return serve.Server._maybe_compact, srv, st, seq, calls
+
+
+def test_compaction_reads_exact_counts_when_the_bound_is_loose(monkeypatch):
+    """The host's last result is old (arrival 0), so its bound on live entries
+    (known + packets added since) passes half a table although the update's
+    exact counts are small: the state is compacted after one synchronisation,
+    not declared too small."""
+    fn, srv, st, seq, calls = _compaction_setup(monkeypatch, exact=[120, 80, 90],
+                                                known=(0, (10, 10, 10)), sizes=[10] + [100] * 7)
+    fn(srv, st, seq)
+    assert srv.s_roll.syncs == 1 and calls == [("state0", "state1")]
+    assert st.si == 1 and st.compactions == 1 and st.occ == [120, 80, 90]
+    assert st.known == (seq, (120, 80, 90))
+
+
+def test_compaction_keeps_the_bound_when_it_suffices(monkeypatch):
+    """A recent result bounds the live entries below half a table: no
+    synchronisation."""
+    fn, srv, st, seq, calls = _compaction_setup(monkeypatch, exact=[0, 0, 0],
+                                                known=(6, (300, 200, 100)), sizes=[100] * 7 + [20])
+    fn(srv, st, seq)
+    assert srv.s_roll.syncs == 0 and len(calls) == 1 and st.occ == [320, 220, 120]
+
+
+def test_compaction_refuses_a_state_that_is_too_small(monkeypatch):
+    """Exact counts past half a table raise."""
+    fn, srv, st, seq, calls = _compaction_setup(monkeypatch, exact=[700, 10, 10],
+                                                known=(0, (10, 10, 10)), sizes=[10] + [100] * 7)
+    with pytest.raises(RuntimeError, match="outgrows"):
+        fn(srv, st, seq)
+    assert srv.s_roll.syncs == 1 and not calls
+
+
 def rolling_want(windows, ring):
     out = []
     for k in range(len(windows)):
