@@ -53,6 +53,9 @@ def parse():
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-secondary", action="store_true",
                    help="skip the smaller workloads' batched-vs-plain entries")
+    p.add_argument("--no-with-per-window", action="store_true",
+                   help="aggregate workloads: skip timing the call that also returns every "
+                        "window's quantities")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="target CPU time of the oracle baseline sample")
     p.add_argument("--serve-arrivals", type=int, default=11024,
@@ -181,24 +184,24 @@ class PlainPath:
             ns.stats(mats[0], self.st_a, self.ws)
 
 
-def bytes_model(N, W, got, got_agg, per_window, aggregate):
+def bytes_model(N, W, got, got_agg, per_window, aggregate, cmin, bits):
     """Bytes the design as built moves for one step, from the measured links,
     sources and destinations of each pipeline that runs:
-      multi-segment sort (look-back): 8 (histogram) + 8 x 16 (key passes)
-      single segment >= CHUNKED_MIN_DEFAULT (chunked): 8 x (8 + 16)
+      sort with look-back: 8 (histogram) + 8 x 16 (key passes)
+      single segment of at least `cmin` keys (chunked, digits of `bits` bits,
+        P = 64 / bits key passes): P x (8 + 16)
       run-length: 8 read + 24 per link (items + the per-window matrix, or the
         aggregate's keys and counts) + 16 per row head
       row maxima: 16 per row head
       columns: 8 per link (histogram; look-back only) + 4 x 16 per link
-        (passes; +8 each when chunked) + 8 per link (run reduce) + 16 per
-        column head, and 16 per column head for the maxima."""
-    from paper_2510_14050_amd import ns
-    cmin = ns.CHUNKED_MIN_DEFAULT
+        (passes; chunked: 32 / bits passes of 8 + 16) + 8 per link (run
+        reduce) + 16 per column head, and 16 per column head for the maxima."""
+    P, Pc = -(-64 // bits), -(-32 // bits)
 
     def pipe(n, links, rows, cols, chunked):
-        b = (8 * 24 if chunked else 8 + 8 * 16) * n
+        b = (P * 24 if chunked else 8 + 8 * 16) * n
         b += 8 * n + 24 * links + 16 * rows + 16 * rows
-        b += (4 * 24 if chunked else 8 + 4 * 16) * links + 8 * links + 32 * cols
+        b += (Pc * 24 if chunked else 8 + 4 * 16) * links + 8 * links + 32 * cols
         return b
     total = 0
     if per_window:
@@ -251,7 +254,7 @@ def profiled_traffic(workload: str, kernel: str):
     return None
 
 
-def path_rates(workload, N, W, got, got_agg, ms_step, per_window, aggregate):
+def path_rates(workload, N, W, got, got_agg, ms_step, per_window, aggregate, cmin, bits):
     """Whole-step rates: measured memory traffic (rocprofv3 FETCH_SIZE +
     WRITE_SIZE of every library kernel of one step, scaled by a 1 GiB copy;
     null unless taken on these sources), the model bytes of the design as
@@ -260,7 +263,7 @@ def path_rates(workload, N, W, got, got_agg, ms_step, per_window, aggregate):
     t = _traffic_file()
     measured = (t or {}).get("step_traffic_bytes", {}).get(workload)
     sec = ms_step * 1e-3
-    M = bytes_model(N, W, got, got_agg, per_window, aggregate)
+    M = bytes_model(N, W, got, got_agg, per_window, aggregate, cmin, bits)
     links = int(got_agg[1]) if aggregate else int(got[:, 1].sum())
     S = survey_bytes(N, links)
     F = 8 * N + 64 * (W if per_window else 1)
@@ -280,20 +283,20 @@ def path_rates(workload, N, W, got, got_agg, ms_step, per_window, aggregate):
 
 
 def radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block, sort_items, workload,
-                   per_window, aggregate):
-    """Roofline of the dominant kernel, the radix pass (key passes 2-8 and the
-    four column passes; the first key pass reads packets and is timed apart).
-    Two kernels implement it: k_pass (decoupled look-back, every multi-segment
-    sort) and k_pass_chunked (one segment of at least CHUNKED_MIN_DEFAULT
-    keys). Algorithmic bytes = one 8-byte read + one 8-byte write per key or
-    column item moved; the report covers whichever kernel took longer, and
-    lists both."""
+                   per_window, aggregate, cmin, bits):
+    """Roofline of the dominant kernel, the radix pass (key passes after the
+    first, which reads packets and is timed apart, and the column passes).
+    Two kernels implement it: k_pass (decoupled look-back, byte digits: 7 + 4
+    passes) and the chunked pass (one segment of at least `cmin` keys, digits
+    of `bits` bits: 64 / bits - 1 + 32 / bits passes). Algorithmic bytes = one
+    8-byte read + one 8-byte write per key or column item moved; the report
+    covers whichever kernel took longer, and lists both."""
     from paper_2510_14050_amd import ns
-    cmin = ns.CHUNKED_MIN_DEFAULT
+    chunk_kernel = "k_pass_chunked" if bits == 8 else "k_pass_chunked_wide"
     fams = {
         "k_pass": {"kernel": f"ns::k_pass<{sort_block}, {sort_items}, false>",
                    "kinds": ("pass", "col_pass"), "items": 0},
-        "k_pass_chunked": {"kernel": "ns::k_pass_chunked<%d, %d, false>" % ns.CHUNKED_SHAPE,
+        "k_pass_chunked": {"kernel": "ns::%s<%d, %d, false>" % ((chunk_kernel,) + ns.CHUNKED_SHAPE),
                            "kinds": ("pass_chunked", "col_pass_chunked"), "items": 0},
     }
     runs = []
@@ -302,7 +305,8 @@ def radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block, sort_items, wor
     if aggregate and not (per_window and W == 1):
         runs.append((N >= cmin, agg_nnz))
     for chunked, links in runs:
-        fams["k_pass_chunked" if chunked else "k_pass"]["items"] += 7 * N + 4 * links
+        P, Pc = (-(-64 // bits), -(-32 // bits)) if chunked else (8, 4)
+        fams["k_pass_chunked" if chunked else "k_pass"]["items"] += (P - 1) * N + Pc * links
     rows = {}
     for name, f in fams.items():
         ms = sum(kt.get(k, (0.0, 0))[0] for k in f["kinds"])
@@ -351,8 +355,12 @@ def run_workload(name, args, dev, primary):
     shape = tune.lookup(N, W, aggregate_only=aggregate and not per_window)
     sort_block = shape.sort_block if shape else 256
     sort_items = shape.sort_items if shape else 16
+    # single segments of at least cmin keys take the chunked passes, on digits of `bits` bits
+    cmin = shape.chunked_min if shape and shape.chunked_min else ns.CHUNKED_MIN_DEFAULT
+    bits = shape.digit_bits if shape and shape.digit_bits else 8
     log(f"launch shape: radix {sort_block}x{sort_items}, scan 256x"
-        f"{shape.scan_items if shape else 8} "
+        f"{shape.scan_items if shape else 8}, digit bits {bits}, "
+        f"chunked from {cmin if cmin < (1 << 63) else 'never'} "
         f"({'autotuned' if shape else 'default: no tuning cache entry'} for {tune._device_name()})")
     out_arg = out if per_window else None
 
@@ -377,7 +385,7 @@ def run_workload(name, args, dev, primary):
         res["aggregate_links"] = agg_nnz
 
     # the same call with every window's quantities as well (aggregate workloads)
-    if primary and aggregate and not per_window:
+    if primary and aggregate and not per_window and not args.no_with_per_window:
         def step_all():
             ns.batch_stats(src_t, dst_t, off_t, out, ws, agg=agg, agg_stats=agg_stats,
                            tune=shape)
@@ -401,10 +409,11 @@ def run_workload(name, args, dev, primary):
         ns.timing_reset()
         links_windows = int(got[:, 1].sum())
         res["roofline"] = radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block,
-                                         sort_items, name, per_window, aggregate)
+                                         sort_items, name, per_window, aggregate, cmin, bits)
         res["kernels_ms"] = {k: {"ms": round(v[0], 4), "launches": v[1]} for k, v in kt.items()}
         log("kernel breakdown (eager, ms):", json.dumps(res["kernels_ms"]))
-        res["path"] = path_rates(name, N, W, got, got_agg, ms_step, per_window, aggregate)
+        res["path"] = path_rates(name, N, W, got, got_agg, ms_step, per_window, aggregate, cmin,
+                                 bits)
 
     if primary and aggregate and not args.no_analysis:
         res["analysis"] = analysis_leg(ns, torch, np, agg, ws, N, got_agg, args, dev)
@@ -499,33 +508,34 @@ def cpu_leg(args, wl, src_t, dst_t, off_np, got, got_agg, per_window, aggregate)
     from paper_2510_14050_amd import synth
     W = wl.num_windows
     host = host_info()
-    # host copies of the packets the sample may use (not timed)
-    lim = int(off_np[min(W, 512)])
-    src = synth.as_u32(src_t[:lim])
-    dst = synth.as_u32(dst_t[:lim])
     bit_exact = True
     if aggregate and not per_window:
-        # the aggregate of the first k windows, k doubling until the budget
-        k, spent, rate = 1, 0.0, None
-        while True:
-            n = int(off_np[k])
-            c0 = time.perf_counter()
-            st = oracle.stats(src[:n], dst[:n])
-            dt = time.perf_counter() - c0
-            spent += dt
-            rate, sample_w, sample_n, sample_t = n / dt, k, n, dt
-            if k == W:
-                bit_exact = bool(np.array_equal(st, got_agg))
-            if spent > args.cpu_seconds / 3 or k >= W or 2 * k > min(W, 512):
-                break
-            k *= 2
+        # the aggregate of the first k windows: a short run sizes k so that the
+        # timed run takes about --cpu-seconds
+        k0 = min(W, 16)
+        n0 = int(off_np[k0])
+        s0, d0 = synth.as_u32(src_t[:n0]), synth.as_u32(dst_t[:n0])
+        c0 = time.perf_counter()
+        oracle.stats(s0, d0)
+        per_pk = (time.perf_counter() - c0) / max(n0, 1)
+        want_n = args.cpu_seconds / max(per_pk, 1e-12) / 1.15  # n log n grows a little
+        k = int(np.searchsorted(off_np, want_n, side="right")) - 1
+        k = max(k0, min(W, k))
+        sample_n = int(off_np[k])
+        src = synth.as_u32(src_t[:sample_n])
+        dst = synth.as_u32(dst_t[:sample_n])
+        c0 = time.perf_counter()
+        st = oracle.stats(src, dst)
+        sample_t = time.perf_counter() - c0
+        rate, sample_w = sample_n / sample_t, k
+        if k == W:
+            bit_exact = bool(np.array_equal(st, got_agg))
         # parity of the sampled windows' quantities comes from the GPU tests; the
         # sample here checks every window the per-window call produced
         if got is not None and got.any():
             for w in (0, W - 1):
                 a, b = int(off_np[w]), int(off_np[w + 1])
-                s_w, d_w = (src[a:b], dst[a:b]) if b <= lim else \
-                    (synth.as_u32(src_t[a:b]), synth.as_u32(dst_t[a:b]))
+                s_w, d_w = synth.as_u32(src_t[a:b]), synth.as_u32(dst_t[a:b])
                 bit_exact = bit_exact and bool(np.array_equal(got[w], oracle.stats(s_w, d_w)))
         cpu = {"value": rate, "unit": "packets/s", "cores": 1, "kind": "oracle",
                "sample": f"aggregate of the first {sample_w} of {W} windows ({sample_n} "
@@ -534,6 +544,10 @@ def cpu_leg(args, wl, src_t, dst_t, off_np, got, got_agg, per_window, aggregate)
                "windows_sampled": sample_w, "host": host}
         log(f"oracle: {rate:.4e} packets/s on the aggregate of {sample_w} windows")
         return cpu, bit_exact
+    # host copies of the packets the sample may use (not timed)
+    lim = int(off_np[min(W, 512)])
+    src = synth.as_u32(src_t[:lim])
+    dst = synth.as_u32(dst_t[:lim])
     c0 = time.perf_counter()
     want = []
     w = 0
@@ -599,11 +613,14 @@ def stream_leg(args, ns, torch, src_t, dst_t, agg, ws, dev):
     sws = ns.StreamWorkspace(batch, out.capacity, device=dev)
     cs = torch.cuda.Stream(device=dev)
     reps = 3
+    status_before = ns.device_status()  # reads and clears what earlier legs left
     ms = timed_loop(torch, lambda: ns.build_matrix_streamed(src_h, dst_h, out, sws,
                                                             copy_stream=cs), reps, 1)
-    same = ns.device_status() == 0 and out.nnz() == links and \
-        bool(torch.equal(out.keys[:links], agg.keys[:links])) and \
-        bool(torch.equal(out.counts[:links], agg.counts[:links]))
+    status = ns.device_status()
+    nnz = out.nnz()
+    keys_eq = nnz == links and bool(torch.equal(out.keys[:links], agg.keys[:links]))
+    counts_eq = nnz == links and bool(torch.equal(out.counts[:links], agg.counts[:links]))
+    same = status == 0 and keys_eq and counts_eq
     sd, dd = torch.empty_like(src_t), torch.empty_like(dst_t)
 
     def h2d():
@@ -617,6 +634,8 @@ def stream_leg(args, ns, torch, src_t, dst_t, agg, ws, dev):
            "h2d_ms": round(h2d_ms, 4), "h2d_gbs": round(8 * N / (h2d_ms * 1e-3) / 1e9, 1),
            "device_resident_build_ms": round(build_ms, 4),
            "same_as_batched_aggregate": same,
+           "check": {"status": status, "status_before": status_before, "nnz": nnz,
+                     "nnz_batched": links, "keys_equal": keys_eq, "counts_equal": counts_eq},
            "what": "ns_build_matrix_streamed from pinned host memory (copies on a second stream)"}
     log(f"out-of-core build: {ms:.3f} ms for {N} packets in {res['sub_partitions']} "
         f"sub-partitions (copy alone {h2d_ms:.3f} ms, device-resident build {build_ms:.3f} ms)")
