@@ -605,6 +605,126 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 }
 
 // ---------------------------------------------------------------------------
+// Radix pass over a single segment with the next tile ranked early.
+//
+// On one segment every tile's look-back goes back to the tile before it, so
+// a tile's counts must be published as soon as possible after its ticket is
+// drawn. k_pass either draws the next ticket after the scatter (its keys then
+// arrive while nothing else happens) or early (its counts then wait behind the
+// whole scatter). Here a workgroup draws the next ticket before the current
+// tile's look-back, requests its keys, and ranks it and publishes its counts
+// right after that look-back, before it scatters the current tile: the key
+// loads overlap the look-back, waves without a digit to resolve rank at once,
+// and the held tile's counts are out one ranking after its keys arrive. The
+// held tile's key positions in the tile wait in registers until the current
+// tile's keys have left LDS. A held ticket is still safe: its holder has
+// published the counts of its current tile and resolves that tile's prefix
+// from smaller tickets only.
+// ---------------------------------------------------------------------------
+template <int BLOCK, int ITEMS, bool PACKETS>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_pass1(PassArgs a) {
+  constexpr int TILE = BLOCK * ITEMS;
+  constexpr int NW = BLOCK / kWave;
+  static_assert(BLOCK >= kBins, "one thread per digit");
+  __shared__ uint64_t s_keys[TILE];
+  __shared__ uint32_t s_wcnt[NW][kBins];
+  __shared__ uint32_t s_part[kBins / kWave];
+  __shared__ uint64_t s_gdel[kBins];
+  __shared__ uint32_t s_tile;
+
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const uint32_t shift = a.shift;
+  const uint64_t tiles = ld_const(a.tile_off + 1);
+  const uint64_t seg_lo = ld_const(a.seg_off), seg_hi = ld_const(a.seg_off + 1);
+  const uint32_t wbase = wv * (kWave * ITEMS);
+
+  auto draw = [&]() {
+    if (tid == 0) {
+      const uint32_t k = atomicAdd(a.ticket, 1u);
+      s_tile = k < tiles ? k : 0xFFFFFFFFu;
+    }
+  };
+  auto tile_keys = [&](uint32_t t) {
+    const uint64_t start = seg_lo + (uint64_t)t * TILE;
+    return (uint32_t)min((uint64_t)TILE, seg_hi - start);
+  };
+  // rank the tile held in `key`, publish its digit counts, and turn the ranks
+  // into LDS positions, two 16-bit positions per register (0xFFFF: no key)
+  static_assert(TILE < 0xFFFF && ITEMS % 2 == 0, "16-bit tile positions");
+  uint64_t key[ITEMS];
+  uint32_t pos[ITEMS / 2];
+  auto rank_and_publish = [&](uint32_t t, uint32_t n, uint32_t *tot, uint32_t *lstart) {
+    uint32_t dig[ITEMS], rank[ITEMS];
+    const bool full = n == TILE;
+    if (full) rank_tile<ITEMS, true>(key, shift, n, wbase, lane, dig, rank, s_wcnt[wv]);
+    else rank_tile<ITEMS, false>(key, shift, n, wbase, lane, dig, rank, s_wcnt[wv]);
+    __syncthreads();
+    tile_offsets<NW>(s_wcnt, s_part, tid, tot, lstart, [&](uint32_t sum) {
+      lb_store(a.lb + (uint64_t)t * kBins + tid, (t == 0 ? kLbInc : kLbAgg) | sum);
+    });
+#pragma unroll
+    for (int k = 0; k < ITEMS; k += 2) {
+      const uint32_t p0 = dig[k] < kBins ? s_wcnt[wv][dig[k]] + rank[k] : 0xFFFFu;
+      const uint32_t p1 = dig[k + 1] < kBins ? s_wcnt[wv][dig[k + 1]] + rank[k + 1] : 0xFFFFu;
+      pos[k / 2] = p0 | (p1 << 16);
+    }
+  };
+  // the held tile's keys into LDS, counters cleared for the next ranking
+  // (after a barrier that ends every read of s_keys and s_wcnt)
+  auto place = [&]() {
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t p = (pos[k / 2] >> (16 * (k & 1))) & 0xFFFFu;
+      if (p != 0xFFFFu) s_keys[p] = key[k];
+    }
+    for (int i = tid; i < NW * kBins; i += BLOCK) (&s_wcnt[0][0])[i] = 0;
+  };
+
+  for (int i = tid; i < NW * kBins; i += BLOCK) (&s_wcnt[0][0])[i] = 0;
+  draw();
+  __syncthreads();
+  uint32_t t = __builtin_amdgcn_readfirstlane(s_tile);
+  if (t == 0xFFFFFFFFu) return;
+  uint32_t n = tile_keys(t);
+  pass_load<ITEMS, PACKETS>(a, seg_lo + (uint64_t)t * TILE, n, wbase, lane, TILE, key);
+  uint32_t tot = 0, lstart = 0;
+  rank_and_publish(t, n, &tot, &lstart);
+  __syncthreads();
+  place();
+
+  for (;;) {
+    draw();
+    __syncthreads();  // the ticket; tile t in LDS; counters clear
+    const uint32_t t2 = __builtin_amdgcn_readfirstlane(s_tile);
+    uint32_t n2 = 0;
+    if (t2 != 0xFFFFFFFFu) {
+      n2 = tile_keys(t2);
+      pass_load<ITEMS, PACKETS>(a, seg_lo + (uint64_t)t2 * TILE, n2, wbase, lane, TILE, key);
+    }
+    if (tid < kBins) {
+      uint64_t excl = 0;
+      if (t != 0) {
+        excl = lb_walkn<NS_LB_DEPTH>(a.lb, kBins, tid, t, 0);
+        lb_store(a.lb + (uint64_t)t * kBins + tid, kLbInc | (excl + tot));
+      }
+      s_gdel[tid] = seg_lo + a.base[tid] + excl - lstart;
+      a.lb_next[(uint64_t)t * kBins + tid] = 0;
+    }
+    uint32_t tot2 = 0, lstart2 = 0;
+    if (t2 != 0xFFFFFFFFu) rank_and_publish(t2, n2, &tot2, &lstart2);  // ends with a barrier
+    else __syncthreads();
+    write_tile<BLOCK, ITEMS>(s_keys, s_gdel, n, shift, tid, a.out, a.lim);
+    if (t2 == 0xFFFFFFFFu) break;
+    __syncthreads();
+    place();
+    t = t2;
+    n = n2;
+    tot = tot2;
+    lstart = lstart2;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Radix pass over one large segment without look-back (reduce, scan, scatter).
 //
 // With a single segment, every tile's look-back walks a long chain of tiles
@@ -1873,8 +1993,27 @@ static hipError_t pass_impl(const PassArgs &a, uint64_t max_tiles, hipStream_t s
   return hipGetLastError();
 }
 
+template <int B, int I, bool P>
+static hipError_t pass1_impl(const PassArgs &a, uint64_t max_tiles, hipStream_t s) {
+  static uint64_t cap[64];
+  const int d = device_id();
+  if (!cap[d]) cap[d] = resident(k_pass1<B, I, P>, B);
+  NS_LAUNCH((k_pass1<B, I, P>), dim3(clamp_grid(max_tiles, cap[d])), dim3(B), s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_pass(const SortShape &sh, const PassArgs &a, uint64_t max_tiles, hipStream_t s) {
   const bool P = a.src != nullptr;
+  // one segment of at least 2^28 keys: the early-ranking pass (2^30 keys:
+  // 46.5 vs 47.7 ms per aggregate step; below 2^28 it was slower, 6.32 vs
+  // 6.23 ms at 2^27 and 1.06 vs 1.02 ms at 2^24)
+  if (a.W == 1 && a.lim >= (1ull << 28)) {
+    if (sh.block == 256 && sh.items == 8) return P ? pass1_impl<256, 8, true>(a, max_tiles, s) : pass1_impl<256, 8, false>(a, max_tiles, s);
+    if (sh.block == 256 && sh.items == 16) return P ? pass1_impl<256, 16, true>(a, max_tiles, s) : pass1_impl<256, 16, false>(a, max_tiles, s);
+    if (sh.block == 512 && sh.items == 8) return P ? pass1_impl<512, 8, true>(a, max_tiles, s) : pass1_impl<512, 8, false>(a, max_tiles, s);
+    if (sh.block == 512 && sh.items == 16) return P ? pass1_impl<512, 16, true>(a, max_tiles, s) : pass1_impl<512, 16, false>(a, max_tiles, s);
+    return hipErrorInvalidValue;
+  }
   if (sh.block == 256 && sh.items == 8) return P ? pass_impl<256, 8, true>(a, max_tiles, s) : pass_impl<256, 8, false>(a, max_tiles, s);
   if (sh.block == 256 && sh.items == 16) return P ? pass_impl<256, 16, true>(a, max_tiles, s) : pass_impl<256, 16, false>(a, max_tiles, s);
   if (sh.block == 512 && sh.items == 8) return P ? pass_impl<512, 8, true>(a, max_tiles, s) : pass_impl<512, 8, false>(a, max_tiles, s);

@@ -1,7 +1,8 @@
 """Full-size checks: the 2^30-packet aggregate (8192 windows of 2^17 with a
 scanner and a sink) in the benchmark's launch configuration, every output
-compared with the oracle; and, past 2^31 packets or entries, one window, a
-batch of 32769 windows and a union-add, all with closed-form answers.
+compared with the oracle; one segment of 2^28 + 12345 packets, against the
+oracle; and, past 2^31 packets or entries, one window, a batch of 32769
+windows and a union-add, all with closed-form answers.
 
 At 2^30 packets the oracle builds the aggregate in source ranges: the packets
 are cut by the top 16 bits of their source into ranges of about 2^23 packets
@@ -41,6 +42,81 @@ def source_ranges(hist: np.ndarray, target: int):
         acc += int(hist[p])
     out.append((lo, hist.size))
     return out
+
+
+def oracle_matrix_by_source_ranges(torch, src_t, dst_t, keys, counts, pool, target=1 << 23):
+    """Compare a GPU matrix (host keys and counts) with the oracle's matrix of
+    the same packets, built in source ranges on the pool's threads; returns the
+    oracle's keys and counts."""
+    s64 = src_t.to(torch.int64) & 0xFFFFFFFF
+    hist = torch.bincount(s64 >> 16, minlength=1 << 16).cpu().numpy()
+    ranges = source_ranges(hist, target)
+    order = sorted(range(len(ranges)), key=lambda i: -int(hist[ranges[i][0]:ranges[i][1]].sum()))
+    jobs = [None] * len(ranges)
+    for i in order:  # largest ranges first, so the longest sorts start early
+        lo, hi = ranges[i]
+        m = (s64 >= (lo << 16)) & (s64 < (hi << 16))
+        bs, bd = synth.as_u32(src_t[m]), synth.as_u32(dst_t[m])
+        assert bs.size == int(hist[lo:hi].sum())
+        jobs[i] = pool.submit(oracle.build_matrix, bs, bd)
+    del s64, m
+    say(len(ranges), "source ranges; comparing the matrix range by range")
+    ok_keys, ok_counts = [], []
+    for (lo, hi), j in zip(ranges, jobs):
+        k, c = j.result()
+        a = int(np.searchsorted(keys, np.uint64(lo) << np.uint64(48)))
+        b = int(np.searchsorted(keys, np.uint64(hi) << np.uint64(48))) if hi < (1 << 16) \
+            else keys.size
+        assert np.array_equal(keys[a:b], k), (lo, hi)
+        assert np.array_equal(counts[a:b], c), (lo, hi)
+        ok_keys.append(k)
+        ok_counts.append(c)
+    assert sum(k.size for k in ok_keys) == keys.size
+    return np.concatenate(ok_keys), np.concatenate(ok_counts)
+
+
+def test_single_segment_past_2p28_early_ranking():
+    """One segment of 2^28 + 12345 packets: single segments of at least 2^28
+    keys take the early-ranking radix pass (first pass with a ragged last
+    tile, seven more key passes, and the column passes of its links). The
+    matrix and its eight quantities against the oracle's, built in source
+    ranges, and the statistics alone through ns_stats."""
+    import torch
+    from paper_2510_14050_amd import ns
+    dev = torch.device("cuda:0")
+    torch.cuda.empty_cache()
+    n = (1 << 28) + 12345
+    wl = synth.Workload("single_2p28", 9, 1 << 22, 1.2, 1.3, np.array([n], np.int64))
+    say("generating", n, "packets on the device")
+    src_t, dst_t = wl.device_concat(dev)
+    off = torch.tensor([0, n], dtype=torch.int64, device=dev)
+    ws = ns.Workspace(n, 1, device=dev)
+    m = ns.Matrix(n, device=dev)
+    st = torch.zeros(8, dtype=torch.int64, device=dev)
+    win_st = torch.zeros((1, 8), dtype=torch.int64, device=dev)
+    never = (1 << 64) - 1
+    say("ns_batch_stats: one segment, look-back passes")
+    ns.batch_stats(src_t, dst_t, off, win_st, ws, agg=m, agg_stats=st,
+                   tune=ns.tuning(sort_block=512, sort_items=16, scan_items=16, chunked_min=never))
+    torch.cuda.synchronize()
+    assert ns.device_status() == 0
+    got = ns.stats_numpy(st).copy()
+    assert ns.stats_numpy(win_st)[0].tolist() == got.tolist()
+    say("ns_stats of the matrix")
+    st2 = torch.zeros(8, dtype=torch.int64, device=dev)
+    ns.stats(m, st2, ws)
+    torch.cuda.synchronize()
+    assert ns.device_status() == 0
+    assert ns.stats_numpy(st2).tolist() == got.tolist()
+    del ws
+    keys, counts = m.numpy()
+    assert keys.size == int(got[1])
+    oracle.build(force=not os.path.exists(oracle.LIB))
+    oracle.stats(synth.as_u32(src_t[:1]), synth.as_u32(dst_t[:1]))
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as pool:
+        ok_k, ok_c = oracle_matrix_by_source_ranges(torch, src_t, dst_t, keys, counts, pool)
+    assert oracle.stats_matrix(ok_k, ok_c).tolist() == got.tolist()
+    assert int(got[0]) == n
 
 
 def test_aggregate_2p30_full_size():
@@ -99,34 +175,11 @@ def test_aggregate_2p30_full_size():
                             dst[int(o[a]):int(o[min(a + 64, W)])],
                             o[a:min(a + 64, W) + 1] - o[a]) for a in range(0, W, 64)]
     say("cutting the packets into source ranges on the device")
-    s64 = src_t.to(torch.int64) & 0xFFFFFFFF
-    hist = torch.bincount(s64 >> 16, minlength=1 << 16).cpu().numpy()
-    ranges = source_ranges(hist, 1 << 23)
-    order = sorted(range(len(ranges)), key=lambda i: -int(hist[ranges[i][0]:ranges[i][1]].sum()))
-    jobs = [None] * len(ranges)
-    for i in order:  # largest ranges first, so the longest sorts start early
-        lo, hi = ranges[i]
-        m = (s64 >= (lo << 16)) & (s64 < (hi << 16))
-        bs, bd = synth.as_u32(src_t[m]), synth.as_u32(dst_t[m])
-        assert bs.size == int(hist[lo:hi].sum())
-        jobs[i] = pool.submit(oracle.build_matrix, bs, bd)
-    del s64, m, src_t, dst_t
+    ok_k, ok_c = oracle_matrix_by_source_ranges(torch, src_t, dst_t, keys, counts, pool)
+    assert keys.size == links
+    del src_t, dst_t
     torch.cuda.empty_cache()
-    say(len(ranges), "source ranges; comparing the matrix range by range")
-    ok_keys, ok_counts = [], []
-    for (lo, hi), j in zip(ranges, jobs):
-        k, c = j.result()
-        a = int(np.searchsorted(keys, np.uint64(lo) << np.uint64(48)))
-        b = int(np.searchsorted(keys, np.uint64(hi) << np.uint64(48))) if hi < (1 << 16) \
-            else keys.size
-        assert np.array_equal(keys[a:b], k), (lo, hi)
-        assert np.array_equal(counts[a:b], c), (lo, hi)
-        ok_keys.append(k)
-        ok_counts.append(c)
-    assert sum(k.size for k in ok_keys) == keys.size == links
     say("the oracle's eight quantities of its own matrix")
-    ok_k, ok_c = np.concatenate(ok_keys), np.concatenate(ok_counts)
-    del ok_keys, ok_counts
     want = oracle.stats_matrix(ok_k, ok_c)
     assert want.tolist() == got.tolist()
     say("every window's quantities")
