@@ -140,23 +140,25 @@ __global__ __launch_bounds__(1024) void k_tiles(const uint64_t *seg_off, uint32_
 // ---------------------------------------------------------------------------
 // Radix sort, step 1: byte-digit histograms of every key, per segment.
 // Packets: digit p of key src<<32|dst is bits [8p, 8p+8): p<4 come from dst,
-// p>=4 from src (8 digits). Column items dst<<32|count: the 4 digits of dst.
-// Each workgroup takes a contiguous range of tiles and counts into LDS; the
-// counters go to the segment's global histogram (one atomic per non-zero bin)
-// only when the range crosses into the next segment and at its end. Four
-// interleaved copies of the counters (chosen by lane) spread the updates of a
-// hot digit, which heavy-tailed traffic produces in every wave, over four
-// addresses in different banks.
+// p>=4 from src. Column items dst<<32|count: the 4 digits of dst. One launch
+// counts the four digits of one 32-bit array (dst, src, or the items' high
+// halves) into rows d0..d0+3 of each segment's histogram, so packets take two
+// launches that each read one array. Each workgroup takes a contiguous range
+// of tiles and counts into LDS; the counters go to the segment's global
+// histogram (one atomic per non-zero bin) only when the range crosses into the
+// next segment and at its end. Eight interleaved copies of the counters
+// (chosen by lane) spread the updates of a hot digit, which heavy-tailed
+// traffic produces in every wave, over eight addresses in different banks;
+// four digits at a time keep them within 32 KiB of LDS.
 // ---------------------------------------------------------------------------
-template <int BLOCK, bool PACKETS>
-__global__ __launch_bounds__(BLOCK) void k_hist(const uint32_t *__restrict__ src,
-                                                const uint32_t *__restrict__ dst,
+template <int BLOCK, bool ITEMS64>
+__global__ __launch_bounds__(BLOCK) void k_hist(const uint32_t *__restrict__ vals,
                                                 const uint64_t *__restrict__ items,
                                                 const uint64_t *seg_off, const uint64_t *tile_off,
-                                                uint32_t W, uint32_t *hist) {
-  constexpr int C = 4;
-  constexpr int ND = PACKETS ? kKeyDigits : kColDigits;
-  constexpr int NC = ND * kBins;
+                                                uint32_t W, uint32_t *hist, uint32_t row_stride,
+                                                uint32_t d0) {
+  constexpr int C = 8;
+  constexpr int NC = 4 * kBins;
   __shared__ uint32_t s_h[NC * C];
   const uint64_t total = ld_const(tile_off + W);
   const uint64_t per = (total + gridDim.x - 1) / gridDim.x;
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(BLOCK) void k_hist(const uint32_t *__restrict__ src
   // together do not queue on the same counters
   const uint32_t rot = (blockIdx.x * BLOCK) % NC;
   auto flush = [&](uint32_t w) {
-    uint32_t *g = hist + (uint64_t)w * NC;
+    uint32_t *g = hist + (uint64_t)w * row_stride + (uint64_t)d0 * kBins;
     for (int i0 = threadIdx.x; i0 < NC; i0 += BLOCK) {
       const int i = (i0 + rot) % NC;
       uint32_t c = 0;
@@ -179,10 +181,6 @@ __global__ __launch_bounds__(BLOCK) void k_hist(const uint32_t *__restrict__ src
       }
       if (c) atomicAdd(&g[i], c);
     }
-  };
-  auto count32 = [&](int d0, uint32_t v) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) atomicAdd(&s_h[((d0 + q) * kBins + ((v >> (8 * q)) & 255)) * C + cp], 1u);
   };
   uint32_t cur = t0 < t1 ? find_owner_wave(tile_off, W, t0) : 0;
   for (uint64_t t = t0; t < t1; ++t) {
@@ -196,29 +194,20 @@ __global__ __launch_bounds__(BLOCK) void k_hist(const uint32_t *__restrict__ src
     }
     const uint64_t start = ld_const(seg_off + w) + (t - ld_const(tile_off + w)) * (uint64_t)kHistTile;
     const uint64_t end = min(start + (uint64_t)kHistTile, ld_const(seg_off + w + 1));
-    constexpr int R = 8;  // keys per thread per round, loads issued together
+    constexpr int R = 8;  // values per thread per round, loads issued together
     for (uint64_t i0 = start + threadIdx.x; i0 < end; i0 += (uint64_t)R * BLOCK) {
-      uint32_t lo[R], hi[R];
+      uint32_t v[R];
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         const uint64_t i = i0 + (uint64_t)k * BLOCK;
-        if (PACKETS) {
-          hi[k] = i < end ? src[i] : 0;
-          lo[k] = i < end ? dst[i] : 0;
-        } else {
-          hi[k] = i < end ? (uint32_t)(items[i] >> 32) : 0;
-          lo[k] = 0;
-        }
+        v[k] = i < end ? (ITEMS64 ? (uint32_t)(items[i] >> 32) : vals[i]) : 0;
       }
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         if (i0 + (uint64_t)k * BLOCK >= end) break;
-        if (PACKETS) {
-          count32(0, lo[k]);
-          count32(4, hi[k]);
-        } else {
-          count32(0, hi[k]);
-        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          atomicAdd(&s_h[(q * kBins + ((v[k] >> (8 * q)) & 255)) * C + cp], 1u);
       }
     }
   }
@@ -1960,9 +1949,15 @@ hipError_t launch_hist_packets(const uint32_t *src, const uint32_t *dst, const u
                                uint32_t *hist, hipStream_t s) {
   static uint64_t cap[64];
   const int d = device_id();
-  if (!cap[d]) cap[d] = resident(k_hist<kHistBlock, true>, kHistBlock);
-  NS_LAUNCH((k_hist<kHistBlock, true>), dim3(clamp_grid(hist_blocks(max_tiles), cap[d])), dim3(kHistBlock), s, src, dst,
-            nullptr, seg_off, tile_off, W, hist);
+  if (!cap[d]) cap[d] = resident(k_hist<kHistBlock, false>, kHistBlock);
+  const dim3 grid(clamp_grid(hist_blocks(max_tiles), cap[d]));
+  const uint32_t stride = kKeyDigits * kBins;
+  NS_LAUNCH((k_hist<kHistBlock, false>), grid, dim3(kHistBlock), s, dst, nullptr, seg_off, tile_off, W,
+            hist, stride, 0u);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  NS_LAUNCH((k_hist<kHistBlock, false>), grid, dim3(kHistBlock), s, src, nullptr, seg_off, tile_off, W,
+            hist, stride, 4u);
   return hipGetLastError();
 }
 
@@ -1971,9 +1966,9 @@ hipError_t launch_hist_items(const uint64_t *items, const uint64_t *seg_off,
                              uint32_t *hist, hipStream_t s) {
   static uint64_t cap[64];
   const int d = device_id();
-  if (!cap[d]) cap[d] = resident(k_hist<kHistBlock, false>, kHistBlock);
-  NS_LAUNCH((k_hist<kHistBlock, false>), dim3(clamp_grid(hist_blocks(max_tiles), cap[d])), dim3(kHistBlock), s, nullptr,
-            nullptr, items, seg_off, tile_off, W, hist);
+  if (!cap[d]) cap[d] = resident(k_hist<kHistBlock, true>, kHistBlock);
+  NS_LAUNCH((k_hist<kHistBlock, true>), dim3(clamp_grid(hist_blocks(max_tiles), cap[d])), dim3(kHistBlock), s, nullptr,
+            items, seg_off, tile_off, W, hist, (uint32_t)(kColDigits * kBins), 0u);
   return hipGetLastError();
 }
 
