@@ -286,15 +286,19 @@ def radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block, sort_items, wor
                    per_window, aggregate, cmin, bits):
     """Roofline of the dominant kernel, the radix pass (key passes after the
     first, which reads packets and is timed apart, and the column passes).
-    Two kernels implement it: k_pass (decoupled look-back, byte digits: 7 + 4
-    passes) and the chunked pass (one segment of at least `cmin` keys, digits
-    of `bits` bits: 64 / bits - 1 + 32 / bits passes). Algorithmic bytes = one
+    Two kernels implement it: the look-back pass (byte digits: 7 + 4 passes;
+    k_pass1 on one segment of at least 2^28 keys, else k_pass) and the
+    chunked pass (one segment of at least `cmin` keys, digits of `bits` bits:
+    64 / bits - 1 + 32 / bits passes). Algorithmic bytes = one
     8-byte read + one 8-byte write per key or column item moved; the report
     covers whichever kernel took longer, and lists both."""
     from paper_2510_14050_amd import ns
     chunk_kernel = "k_pass_chunked" if bits == 8 else "k_pass_chunked_wide"
+    # one segment of at least 2^28 keys takes the early-ranking pass
+    single_only = not per_window or W == 1
+    lb_kernel = "k_pass1" if single_only and N >= (1 << 28) else "k_pass"
     fams = {
-        "k_pass": {"kernel": f"ns::k_pass<{sort_block}, {sort_items}, false>",
+        "k_pass": {"kernel": f"ns::{lb_kernel}<{sort_block}, {sort_items}, false>",
                    "kinds": ("pass", "col_pass"), "items": 0},
         "k_pass_chunked": {"kernel": "ns::%s<%d, %d, false>" % ((chunk_kernel,) + ns.CHUNKED_SHAPE),
                            "kinds": ("pass_chunked", "col_pass_chunked"), "items": 0},
@@ -688,6 +692,24 @@ def serve_leg(args, dev):
         "compactions": rep.compactions,
         "rolling_spot_checks_bit_exact": checks,
     }
+    # where a micro-batch's time goes on the device (event timestamps), from a
+    # second, shorter run with timed events (kept out of the latencies above):
+    # its build (copies in + ns_batch_stats) and its rolling chain
+    del srv
+    torch.cuda.empty_cache()
+    tsrv = serve.Server(ring=1024, max_window=1 << 17, max_batch=16, budget_bytes=4 << 30,
+                        device=dev, timing=True)
+    m = min(n, 2 * args.serve_warm + 1024)
+    trep = tsrv.run(wins[:m], arrivals_s=wl.arrivals[:m] - wl.arrivals[0])
+    skip = len(trep.batches) // 2
+    bsp = np.array([e - s for _, s, e in trep.build_spans[skip:]])
+    rsp = np.array([e - s for _, s, e in trep.roll_spans[skip:]])
+    del tsrv
+    if bsp.size:
+        out["device_ms"] = {"build_p50": round(float(np.percentile(bsp, 50)), 3),
+                            "build_p99": round(float(np.percentile(bsp, 99)), 3),
+                            "rolling_p50": round(float(np.percentile(rsp, 50)), 3),
+                            "rolling_p99": round(float(np.percentile(rsp, 99)), 3)}
     log("serving:", json.dumps(out))
     return out
 
