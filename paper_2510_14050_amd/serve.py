@@ -15,9 +15,10 @@ with the aggregate. The rolling aggregate at arrival k is
 over windows max(0, k-ring+1)..k by arrival sequence, whatever the batching.
 
 Latency of an arrival = time its two result rows are on the host minus its
-arrival time. All computation goes through the libns C ABI
-(ns_batch_stats_eager, ns_rolling_update, ns_rolling_compact, and in merge mode
-ns_accumulate and ns_stats); this module only moves bytes,
+arrival time. All computation goes through the libns C ABI (ns_batch_stats,
+replaying one captured graph per build slot and packet class, or
+ns_batch_stats_eager with graphs=False; ns_rolling_update, ns_rolling_compact,
+and in merge mode ns_accumulate and ns_stats); this module only moves bytes,
 keeps lifetimes and keeps time.
 """
 from __future__ import annotations
@@ -133,11 +134,16 @@ class Server:
                   matrices (held until the window leaves the ring) and 8 B per
                   packet of staging (held until its micro-batch is built). It
                   must hold ring + 2*max_batch windows of max_window packets.
+    graphs        build micro-batches by replaying captured ns_batch_stats
+                  graphs (two fixed slots of max_batch*max_window packets,
+                  24 B per packet each, beside the budget), or launch them
+                  eagerly
     """
 
     def __init__(self, ring: int = 1024, max_window: int = 1 << 17, max_batch: int = 16,
                  budget_bytes: int = 4 << 30, device="cuda", timing: bool = False,
-                 mode: str = "hash", link_slots: int = 1 << 25, address_slots: int = 1 << 23):
+                 mode: str = "hash", link_slots: int = 1 << 25, address_slots: int = 1 << 23,
+                 graphs: bool = False):
         import torch
         self.torch = torch
         assert mode in ("hash", "merge")
@@ -182,6 +188,43 @@ class Server:
         with torch.cuda.stream(self.s_roll):
             ns.build_matrix(self.stage_src[:0], self.stage_dst[:0], self.empty, self.ws_roll)
         self.s_roll.synchronize()
+        # Graph-replayed builds: a micro-batch is padded to max_batch windows
+        # (empty ones) and its packet count rounded up to a power of two of at
+        # least 2^10, and built in one of two fixed slots (inputs, window
+        # matrices, link counts and quantities at fixed addresses), so each
+        # (slot, packet class) pair replays one captured ns_batch_stats graph.
+        # The slot's results are copied out on the build stream before the slot
+        # is used again. All graphs are captured here, from empty batches.
+        self.graphs = graphs
+        if graphs:
+            cap = batch_pk
+            self.classes = []
+            c = 1 << 10
+            while c < cap:
+                self.classes.append(c)
+                c <<= 1
+            self.classes.append(cap)
+            self.gslots = []
+            for _ in range(2):
+                self.gslots.append({
+                    "src": torch.zeros(cap, dtype=torch.int32, device=d),
+                    "dst": torch.zeros(cap, dtype=torch.int32, device=d),
+                    "off": torch.zeros(max_batch + 1, dtype=torch.int64, device=d),
+                    "out": torch.zeros((max_batch, 8), dtype=torch.int64, device=d),
+                    "win": ns.BatchMatrices(cap, max_batch, device=d),
+                })
+            with torch.cuda.stream(self.s_build):
+                for g in self.gslots:
+                    for c in self.classes:
+                        ns.batch_stats(g["src"][:c], g["dst"][:c], g["off"], g["out"],
+                                       self.ws_build, win=g["win"], graph=True)
+            self.s_build.synchronize()
+
+    def _packet_class(self, total: int) -> int:
+        for c in self.classes:
+            if total <= c:
+                return c
+        raise ValueError("micro-batch larger than max_batch * max_window")
 
     # -- one micro-batch ---------------------------------------------------------
     def _submit(self, st, batch, bidx):
@@ -202,25 +245,43 @@ class Server:
         bs = bidx % self.bslots
         self.pin_off[bs, :W + 1] = torch.from_numpy(off)
         ev_b0 = torch.cuda.Event(enable_timing=True) if self.timing else None
+        if self.graphs:
+            self.pin_off[bs, W + 1:] = total  # padding windows are empty
         with torch.cuda.stream(self.s_build):
             if ev_b0 is not None:
                 ev_b0.record(self.s_build)
-            src = self.stage_src[s0:s0 + total]
-            dst = self.stage_dst[s0:s0 + total]
-            src.copy_(self.pin_src[s0:s0 + total], non_blocking=True)
-            dst.copy_(self.pin_dst[s0:s0 + total], non_blocking=True)
-            offs = self.off_dev[bs, :W + 1]
-            offs.copy_(self.pin_off[bs, :W + 1], non_blocking=True)
             wm = ns.BatchMatrices(total, 0, device=self.dev,
                                   keys=self.mat_keys[m0:m0 + max(total, 1)],
                                   counts=self.mat_counts[m0:m0 + max(total, 1)])
-            # per-window link counts live as long as the windows' matrices: a
-            # fresh tensor, kept by the window views and marked as used by the
-            # rolling stream so the allocator never recycles it early
-            wm.nnz = torch.zeros(max(W, 1), dtype=torch.int64, device=self.dev)
-            wm.nnz.record_stream(self.s_roll)
             outs = self.out_dev[bs, :W]
-            ns.batch_stats(src, dst, offs, outs, self.ws_build, win=wm, graph=False)
+            if self.graphs:
+                g = self.gslots[bidx & 1]
+                c = self._packet_class(total)
+                g["src"][:total].copy_(self.pin_src[s0:s0 + total], non_blocking=True)
+                g["dst"][:total].copy_(self.pin_dst[s0:s0 + total], non_blocking=True)
+                g["off"].copy_(self.pin_off[bs], non_blocking=True)
+                ns.batch_stats(g["src"][:c], g["dst"][:c], g["off"], g["out"], self.ws_build,
+                               win=g["win"], graph=True)
+                # out of the slot before its next use (same stream): the window
+                # matrices into the matrix arena, link counts and quantities
+                if total:
+                    wm.keys[:total].copy_(g["win"].keys[:total])
+                    wm.counts[:total].copy_(g["win"].counts[:total])
+                outs.copy_(g["out"][:W])
+                # per-window link counts live as long as the windows' matrices:
+                # a fresh tensor, kept by the window views and marked as used by
+                # the rolling stream so the allocator never recycles it early
+                wm.nnz = g["win"].nnz[:max(W, 1)].clone()
+            else:
+                src = self.stage_src[s0:s0 + total]
+                dst = self.stage_dst[s0:s0 + total]
+                src.copy_(self.pin_src[s0:s0 + total], non_blocking=True)
+                dst.copy_(self.pin_dst[s0:s0 + total], non_blocking=True)
+                offs = self.off_dev[bs, :W + 1]
+                offs.copy_(self.pin_off[bs, :W + 1], non_blocking=True)
+                wm.nnz = torch.zeros(max(W, 1), dtype=torch.int64, device=self.dev)
+                ns.batch_stats(src, dst, offs, outs, self.ws_build, win=wm, graph=False)
+            wm.nnz.record_stream(self.s_roll)
             built = torch.cuda.Event(enable_timing=self.timing)
             built.record(self.s_build)
         st.stage_free.append(built)                 # staging reusable once built
@@ -328,6 +389,7 @@ class Server:
 
         inbox = collections.deque()
         lock = threading.Lock()
+        arrived = threading.Condition(lock)  # wakes the dispatcher on an arrival
         t_start = time.perf_counter()
 
         def feeder():
@@ -336,8 +398,9 @@ class Server:
                     delay = t_start + float(arrivals_s[k]) - time.perf_counter()
                     if delay > 0:
                         time.sleep(delay)
-                with lock:
+                with arrived:
                     inbox.append((k, windows[k][0], windows[k][1], time.perf_counter()))
+                    arrived.notify()
 
         results = [None] * n
         done_q = collections.deque()
@@ -387,7 +450,12 @@ class Server:
                 batch.append(a)
                 total = t2
             if not batch:
-                time.sleep(0.00005)
+                if ready:  # waiting for device memory or result slots
+                    time.sleep(0.00005)
+                else:
+                    with arrived:
+                        if not inbox:
+                            arrived.wait(timeout=0.002)
                 continue
             with lock:
                 for _ in batch:

@@ -136,15 +136,17 @@ def rolling_want(windows, ring):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("mode", ["hash", "merge"])
-def test_serving_alone_and_in_the_mix(mode):
+@pytest.mark.parametrize("mode,graphs", [("hash", True), ("hash", False), ("merge", True)])
+def test_serving_alone_and_in_the_mix(mode, graphs):
+    """Builds replayed from captured graphs (padded batches in fixed slots) or
+    launched eagerly give the same results."""
     import torch
     from paper_2510_14050_amd.serve import Server
     ring, n = 6, 40
     wins = small_windows(n)
     want_roll = rolling_want(wins, ring)
     want_win = [oracle.stats(s, d) for s, d in wins]
-    kw = dict(mode=mode, link_slots=1 << 15, address_slots=1 << 14)
+    kw = dict(mode=mode, link_slots=1 << 15, address_slots=1 << 14, graphs=graphs)
     srv = Server(ring=ring, max_window=1 << 12, max_batch=4, budget_bytes=64 << 20,
                  timing=True, **kw)
     say("serve alone (max_batch 1, serial)", mode)
