@@ -297,8 +297,9 @@ def radix_roofline(kt, N, W, links_windows, agg_nnz, sort_block, sort_items, wor
     # one segment of at least 2^28 keys takes the early-ranking pass
     single_only = not per_window or W == 1
     lb_kernel = "k_pass1" if single_only and N >= (1 << 28) else "k_pass"
+    narrow = "true" if N <= (1 << 31) - 2 else "false"  # 32-bit look-back words
     fams = {
-        "k_pass": {"kernel": f"ns::{lb_kernel}<{sort_block}, {sort_items}, false>",
+        "k_pass": {"kernel": f"ns::{lb_kernel}<{sort_block}, {sort_items}, false, {narrow}>",
                    "kinds": ("pass", "col_pass"), "items": 0},
         "k_pass_chunked": {"kernel": "ns::%s<%d, %d, false>" % ((chunk_kernel,) + ns.CHUNKED_SHAPE),
                            "kinds": ("pass_chunked", "col_pass_chunked"), "items": 0},

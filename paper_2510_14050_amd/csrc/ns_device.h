@@ -21,13 +21,36 @@ constexpr uint64_t kLbAgg = 1ull << 62;
 constexpr uint64_t kLbInc = 2ull << 62;
 constexpr uint64_t kLbVal = (1ull << 62) - 1;
 
-__device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v) {
+template <typename T>
+__device__ __forceinline__ void lb_store(T *p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ uint64_t lb_load(const uint64_t *p) {
-  return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <typename T>
+__device__ __forceinline__ T lb_load(const T *p) {
+  return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// The radix passes' per-digit words come in two widths. 64-bit: status in the
+// top two bits as above. 32-bit, for passes over fewer than 2^31 - 1 keys
+// (half the look-back traffic): 0 = not yet published, bit 31 = inclusive,
+// bits 0..30 = value + 1.
+template <typename W>
+struct LbWord {
+  static __device__ __forceinline__ W agg(uint64_t v) { return kLbAgg | v; }
+  static __device__ __forceinline__ W inc(uint64_t v) { return kLbInc | v; }
+  static __device__ __forceinline__ bool ready(W w) { return (w >> 62) != 0; }
+  static __device__ __forceinline__ bool inclusive(W w) { return (w >> 62) == 2; }
+  static __device__ __forceinline__ uint64_t value(W w) { return w & kLbVal; }
+};
+template <>
+struct LbWord<uint32_t> {
+  static __device__ __forceinline__ uint32_t agg(uint64_t v) { return (uint32_t)v + 1u; }
+  static __device__ __forceinline__ uint32_t inc(uint64_t v) { return 0x80000000u | ((uint32_t)v + 1u); }
+  static __device__ __forceinline__ bool ready(uint32_t w) { return w != 0; }
+  static __device__ __forceinline__ bool inclusive(uint32_t w) { return (w >> 31) != 0; }
+  static __device__ __forceinline__ uint64_t value(uint32_t w) { return (w & 0x7FFFFFFFu) - 1u; }
+};
 
 // ---------------------------------------------------------------------------
 // wave / block helpers
@@ -198,26 +221,27 @@ __device__ __forceinline__ uint32_t find_owner_wave(const uint64_t *off, uint32_
 // an inclusive prefix (tile `first` always does). `stride` is the number of
 // channels per tile. Up to P predecessor words are in flight per round trip
 // (each thread issues the loads of tiles j, j-1, ..., j-P+1 together).
-template <int P>
-__device__ __forceinline__ uint64_t lb_walkn(const uint64_t *lb, uint32_t stride, uint32_t chan,
+template <int P, typename W = uint64_t>
+__device__ __forceinline__ uint64_t lb_walkn(const W *lb, uint32_t stride, uint32_t chan,
                                              uint32_t t, uint32_t first) {
+  using L = LbWord<W>;
   uint64_t excl = 0;
   int64_t j = (int64_t)t - 1;
   while (j >= (int64_t)first) {
-    uint64_t v[P];
+    W v[P];
 #pragma unroll
     for (int q = 0; q < P; ++q)
-      v[q] = (j - q >= (int64_t)first) ? lb_load(lb + (uint64_t)(j - q) * stride + chan) : 0;
+      v[q] = (j - q >= (int64_t)first) ? lb_load(lb + (uint64_t)(j - q) * stride + chan) : W(0);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       if (j - q < (int64_t)first) return excl;
-      const uint64_t *p = lb + (uint64_t)(j - q) * stride + chan;
-      while ((v[q] >> 62) == 0) {
+      const W *p = lb + (uint64_t)(j - q) * stride + chan;
+      while (!L::ready(v[q])) {
         __builtin_amdgcn_s_sleep(1);
         v[q] = lb_load(p);
       }
-      excl += v[q] & kLbVal;
-      if ((v[q] >> 62) == 2) return excl;
+      excl += L::value(v[q]);
+      if (L::inclusive(v[q])) return excl;
     }
     j -= P;
   }

@@ -470,8 +470,12 @@ __device__ __forceinline__ void pass_load(const PassArgs &a, uint64_t start, uin
   }
 }
 
-template <int BLOCK, int ITEMS, bool PACKETS>
+template <int BLOCK, int ITEMS, bool PACKETS, bool W32>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_pass(PassArgs a) {
+  using LW = std::conditional_t<W32, uint32_t, uint64_t>;  // look-back word width
+  using L = LbWord<LW>;
+  LW *const lbw = reinterpret_cast<LW *>(a.lb);
+  LW *const lbn = reinterpret_cast<LW *>(a.lb_next);
   constexpr int TILE = BLOCK * ITEMS;
   constexpr int NW = BLOCK / kWave;
   static_assert(BLOCK >= kBins, "one thread per digit");
@@ -525,7 +529,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     uint32_t tot = 0, lstart = 0;
     // publish this tile's digit counts as early as possible
     tile_offsets<NW>(s_wcnt, s_part, tid, &tot, &lstart, [&](uint32_t sum) {
-      lb_store(a.lb + (uint64_t)t * kBins + tid, (t == first ? kLbInc : kLbAgg) | sum);
+      lb_store(lbw + (uint64_t)t * kBins + tid, t == first ? L::inc(sum) : L::agg(sum));
     });
     // local counting sort of the tile into LDS; the key registers are free after
     if (full) place_tile<ITEMS, true>(key, dig, rank, s_wcnt[wv], s_keys);
@@ -557,11 +561,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     if (tid < kBins) {
       uint64_t excl = 0;
       if (t != first) {
-        excl = lb_walkn<NS_LB_DEPTH>(a.lb, kBins, tid, t, first);
-        lb_store(a.lb + (uint64_t)t * kBins + tid, kLbInc | (excl + tot));
+        excl = lb_walkn<NS_LB_DEPTH>(lbw, kBins, tid, t, first);
+        lb_store(lbw + (uint64_t)t * kBins + tid, L::inc(excl + tot));
       }
       s_gdel[tid] = seg_lo + a.base[(uint64_t)w * a.base_stride + tid] + excl - lstart;
-      a.lb_next[(uint64_t)t * kBins + tid] = 0;
+      lbn[(uint64_t)t * kBins + tid] = 0;
     }
     __syncthreads();
     write_tile<BLOCK, ITEMS>(s_keys, s_gdel, n, shift, tid, a.out, a.lim);
@@ -610,8 +614,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 // published the counts of its current tile and resolves that tile's prefix
 // from smaller tickets only.
 // ---------------------------------------------------------------------------
-template <int BLOCK, int ITEMS, bool PACKETS>
+template <int BLOCK, int ITEMS, bool PACKETS, bool W32>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_pass1(PassArgs a) {
+  using LW = std::conditional_t<W32, uint32_t, uint64_t>;  // look-back word width
+  using L = LbWord<LW>;
+  LW *const lbw = reinterpret_cast<LW *>(a.lb);
+  LW *const lbn = reinterpret_cast<LW *>(a.lb_next);
   constexpr int TILE = BLOCK * ITEMS;
   constexpr int NW = BLOCK / kWave;
   static_assert(BLOCK >= kBins, "one thread per digit");
@@ -649,7 +657,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     else rank_tile<ITEMS, false>(key, shift, n, wbase, lane, dig, rank, s_wcnt[wv]);
     __syncthreads();
     tile_offsets<NW>(s_wcnt, s_part, tid, tot, lstart, [&](uint32_t sum) {
-      lb_store(a.lb + (uint64_t)t * kBins + tid, (t == 0 ? kLbInc : kLbAgg) | sum);
+      lb_store(lbw + (uint64_t)t * kBins + tid, t == 0 ? L::inc(sum) : L::agg(sum));
     });
 #pragma unroll
     for (int k = 0; k < ITEMS; k += 2) {
@@ -693,11 +701,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     if (tid < kBins) {
       uint64_t excl = 0;
       if (t != 0) {
-        excl = lb_walkn<NS_LB_DEPTH>(a.lb, kBins, tid, t, 0);
-        lb_store(a.lb + (uint64_t)t * kBins + tid, kLbInc | (excl + tot));
+        excl = lb_walkn<NS_LB_DEPTH>(lbw, kBins, tid, t, 0);
+        lb_store(lbw + (uint64_t)t * kBins + tid, L::inc(excl + tot));
       }
       s_gdel[tid] = seg_lo + a.base[tid] + excl - lstart;
-      a.lb_next[(uint64_t)t * kBins + tid] = 0;
+      lbn[(uint64_t)t * kBins + tid] = 0;
     }
     uint32_t tot2 = 0, lstart2 = 0;
     if (t2 != 0xFFFFFFFFu) rank_and_publish(t2, n2, &tot2, &lstart2);  // ends with a barrier
@@ -1979,12 +1987,18 @@ hipError_t launch_hist_scan(const uint32_t *hist, uint32_t *base, uint64_t rows,
   return hipGetLastError();
 }
 
+// 32-bit look-back words while every count + 1 fits in 31 bits
+constexpr uint64_t kLbNarrowMax = (1ull << 31) - 2;
+
 template <int B, int I, bool P>
 static hipError_t pass_impl(const PassArgs &a, uint64_t max_tiles, hipStream_t s) {
   static uint64_t cap[64];
   const int d = device_id();
-  if (!cap[d]) cap[d] = resident(k_pass<B, I, P>, B);
-  NS_LAUNCH((k_pass<B, I, P>), dim3(clamp_grid(max_tiles, cap[d])), dim3(B), s, a);
+  if (!cap[d]) cap[d] = resident(k_pass<B, I, P, true>, B);
+  if (a.lim <= kLbNarrowMax)
+    NS_LAUNCH((k_pass<B, I, P, true>), dim3(clamp_grid(max_tiles, cap[d])), dim3(B), s, a);
+  else
+    NS_LAUNCH((k_pass<B, I, P, false>), dim3(clamp_grid(max_tiles, cap[d])), dim3(B), s, a);
   return hipGetLastError();
 }
 
@@ -1992,8 +2006,11 @@ template <int B, int I, bool P>
 static hipError_t pass1_impl(const PassArgs &a, uint64_t max_tiles, hipStream_t s) {
   static uint64_t cap[64];
   const int d = device_id();
-  if (!cap[d]) cap[d] = resident(k_pass1<B, I, P>, B);
-  NS_LAUNCH((k_pass1<B, I, P>), dim3(clamp_grid(max_tiles, cap[d])), dim3(B), s, a);
+  if (!cap[d]) cap[d] = resident(k_pass1<B, I, P, true>, B);
+  if (a.lim <= kLbNarrowMax)
+    NS_LAUNCH((k_pass1<B, I, P, true>), dim3(clamp_grid(max_tiles, cap[d])), dim3(B), s, a);
+  else
+    NS_LAUNCH((k_pass1<B, I, P, false>), dim3(clamp_grid(max_tiles, cap[d])), dim3(B), s, a);
   return hipGetLastError();
 }
 
