@@ -165,7 +165,7 @@ MergeLayout merge_plan(uint64_t n) {
 // around every launch of the eager paths (never inside a captured graph).
 enum Kind { K_FILL, K_TILES, K_HIST, K_HSCAN, K_PASS0, K_PASS, K_CPASS, K_RLE, K_RUNS, K_SEGMAX,
             K_FINAL, K_MERGE, K_CHUNK_COUNT, K_PASS0_CHUNKED, K_PASS_CHUNKED, K_CPASS_CHUNKED,
-            K_COUNT };
+            K_SMALL, K_COUNT };
 
 struct Profiler {
   std::mutex mu;
@@ -621,7 +621,14 @@ int enqueue_batch(const BatchArgs &b, Ws &ws, Ws &ws2, hipStream_t s, hipStream_
     if (rc) return rc;
     if (split) HIP_TRY(hipEventRecord(join, s2));
   }
-  if (b.W > 0) {
+  if (b.W > 0 && b.N <= kSmallMax) {
+    // a small batch: every window's whole pipeline in one workgroup, one launch
+    HIP_TRY(timed(K_SMALL, s, [&] {
+      return launch_small(b.src, b.dst, b.offsets, b.W, reinterpret_cast<uint64_t *>(b.out),
+                          b.win ? b.win->keys : nullptr, b.win ? b.win->counts : nullptr,
+                          b.win ? b.win->nnz : nullptr, s);
+    }));
+  } else if (b.W > 0) {
     PacketOut o{};
     o.stats = reinterpret_cast<uint64_t *>(b.out);
     o.sort_a = ws.at<uint64_t>(ws.L.KA);

@@ -1472,6 +1472,211 @@ void k_runs(RunArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Batches of at most kSmallMax packets in total: each window goes through the
+// whole per-window pipeline inside one workgroup and its LDS, in one launch
+// (the multi-kernel pipeline spends most of such a batch starting and
+// draining some twenty-five launches). Steps, all on LDS: the stable LSD
+// radix sort of the packed keys (8 byte-digit passes with the same wave
+// ranking as the radix passes, keys in registers between passes, the LDS
+// array as the scatter target); link and row heads by comparing neighbours
+// in the sorted keys, ranked by a block scan; each link's count (distance to
+// the next link head) and key, written as the window's matrix at its packet
+// offset; row maxima from consecutive row heads; the column items
+// destination << 32 | count sorted by destination (4 passes); column heads,
+// and per column the packet sum and link count accumulated in LDS (both
+// below 2^16 here, so one 32-bit word holds the pair); then the eight
+// quantities of Table I and Sec. IV. Windows go to workgroups round robin.
+// ---------------------------------------------------------------------------
+template <int ITEMS, int NW>
+__device__ __forceinline__ void small_sort(uint64_t (&key)[ITEMS], uint32_t n, uint32_t shift0,
+                                           int passes, uint64_t *s_keys,
+                                           uint32_t (*s_wcnt)[kBins], uint32_t *s_part) {
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const uint32_t wbase = wv * (kWave * ITEMS);
+  for (int p = 0; p < passes; ++p) {
+    uint32_t dig[ITEMS], rank[ITEMS];
+    rank_tile<ITEMS, false>(key, shift0 + 8 * p, n, wbase, lane, dig, rank, s_wcnt[wv]);
+    __syncthreads();
+    uint32_t tot, lstart;
+    tile_offsets<NW>(s_wcnt, s_part, tid, &tot, &lstart, [](uint32_t) {});
+    place_tile<ITEMS, false>(key, dig, rank, s_wcnt[wv], s_keys);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t i = wbase + k * kWave + lane;
+      key[k] = i < n ? s_keys[i] : 0;
+    }
+    for (int i = tid; i < NW * kBins; i += NW * kWave) (&s_wcnt[0][0])[i] = 0;
+    __syncthreads();
+  }
+}
+
+template <int NW>
+__device__ __forceinline__ uint64_t block_max(uint64_t v, uint64_t *s_tmp) {
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  v = wave_max(v);
+  if (lane == 0) s_tmp[wv] = v;
+  __syncthreads();
+  uint64_t m = 0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) m = s_tmp[q] > m ? s_tmp[q] : m;
+  __syncthreads();
+  return m;
+}
+
+__global__ __launch_bounds__(kSmallBlock) void k_small(const uint32_t *src, const uint32_t *dst,
+                                                       const uint64_t *off, uint32_t W,
+                                                       uint64_t *stats, uint64_t *win_keys,
+                                                       uint64_t *win_counts, uint64_t *win_nnz) {
+  constexpr int BLOCK = kSmallBlock, ITEMS = kSmallMax / kSmallBlock, NW = BLOCK / kWave;
+  constexpr uint32_t TILE = kSmallMax;
+  static_assert(BLOCK >= kBins && ITEMS <= 32, "tile layout");
+  __shared__ uint64_t s_keys[TILE];        // sort target; then the column items
+  __shared__ uint32_t s_wcnt[NW][kBins];
+  __shared__ uint32_t s_part[kBins / kWave];
+  __shared__ uint16_t s_hpos[TILE];        // link head positions
+  __shared__ uint32_t s_aux[TILE];         // row heads (position << 16 | link rank), then columns
+  __shared__ uint64_t s_tmp[NW];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const uint32_t wbase = wv * (kWave * ITEMS);
+  for (int i = tid; i < NW * kBins; i += BLOCK) (&s_wcnt[0][0])[i] = 0;
+  __syncthreads();
+  for (uint32_t w = blockIdx.x; w < W; w += gridDim.x) {
+    const uint64_t lo = off[w];
+    const uint64_t n64 = off[w + 1] - lo;
+    if (n64 > TILE) {  // the host sends only batches that fit
+      if (tid == 0) atomicOr(&g_status, 2);
+      continue;
+    }
+    const uint32_t n = (uint32_t)n64;
+    // 1. keys, sorted
+    uint64_t key[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t i = wbase + k * kWave + lane;
+      key[k] = i < n ? pack_key(src[lo + i], dst[lo + i]) : 0;
+    }
+    small_sort<ITEMS, NW>(key, n, 0, 8, s_keys, s_wcnt, s_part);
+    // 2. link and row heads (each thread: ITEMS consecutive positions)
+    const uint32_t p0 = tid * ITEMS;
+    uint32_t lmask = 0, rmask = 0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t p = p0 + k;
+      if (p < n) {
+        const uint64_t cur = s_keys[p];
+        const uint64_t prev = p ? s_keys[p - 1] : cur ^ 0xFFFFFFFF00000001ull;
+        lmask |= (uint32_t)(cur != prev) << k;
+        rmask |= (uint32_t)((cur >> 32) != (prev >> 32)) << k;
+      }
+    }
+    uint64_t tot;
+    const uint64_t x = block_excl_scan<BLOCK>(((uint64_t)__popc(rmask) << 32) | __popc(lmask),
+                                              s_tmp, &tot);
+    const uint32_t TL = (uint32_t)tot, TR = (uint32_t)(tot >> 32);
+    {
+      uint32_t jl = (uint32_t)x, jr = (uint32_t)(x >> 32);
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        if (rmask & (1u << k)) s_aux[jr++] = ((p0 + k) << 16) | jl;
+        if (lmask & (1u << k)) s_hpos[jl++] = (uint16_t)(p0 + k);
+      }
+    }
+    __syncthreads();
+    // 3. links: the window's matrix and its column items (kept in registers)
+    uint64_t item[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const uint32_t r = tid + j * BLOCK;
+      item[j] = 0;
+      if (r < TL) {
+        const uint32_t pos = s_hpos[r];
+        const uint32_t e = r + 1 < TL ? s_hpos[r + 1] : n;
+        const uint64_t K = s_keys[pos];
+        const uint32_t cnt = e - pos;
+        if (win_keys) {
+          win_keys[lo + r] = K;
+          win_counts[lo + r] = cnt;
+        }
+        item[j] = (K << 32) | cnt;
+      }
+    }
+    // 4. rows: packets and links between consecutive row heads
+    uint64_t mpk = 0, mfan = 0;
+    for (uint32_t q = tid; q < TR; q += BLOCK) {
+      const uint32_t a = s_aux[q];
+      const uint32_t b = q + 1 < TR ? s_aux[q + 1] : (n << 16) | TL;
+      const uint64_t pk = (b >> 16) - (a >> 16), fan = (b & 0xFFFFu) - (a & 0xFFFFu);
+      mpk = pk > mpk ? pk : mpk;
+      mfan = fan > mfan ? fan : mfan;
+    }
+    __syncthreads();  // s_keys, s_hpos and s_aux are free
+    // 5. column items sorted by destination
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const uint32_t r = tid + j * BLOCK;
+      if (r < TL) s_keys[r] = item[j];
+    }
+    for (uint32_t i = tid; i < TL; i += BLOCK) s_aux[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t i = wbase + k * kWave + lane;
+      key[k] = i < TL ? s_keys[i] : 0;
+    }
+    small_sort<ITEMS, NW>(key, TL, 32, 4, s_keys, s_wcnt, s_part);
+    // 6. columns: heads ranked by a block scan, packet sum and link count per
+    // column accumulated in LDS (sum << 16 | count, each below 2^16)
+    uint32_t cmask = 0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t p = p0 + k;
+      if (p < TL) cmask |= (uint32_t)(p == 0 || (s_keys[p] >> 32) != (s_keys[p - 1] >> 32)) << k;
+    }
+    uint64_t ctot;
+    const uint32_t xc = (uint32_t)block_excl_scan<BLOCK>((uint64_t)__popc(cmask), s_tmp, &ctot);
+    const uint32_t TC = (uint32_t)ctot;
+    {
+      int64_t c = (int64_t)xc - 1;  // a thread's first item continues the column before it
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t p = p0 + k;
+        if (p < TL) {
+          c += (cmask >> k) & 1;
+          atomicAdd(&s_aux[c], (uint32_t)((s_keys[p] & 0xFFFFFFFFu) << 16) | 1u);
+        }
+      }
+    }
+    __syncthreads();
+    uint64_t mdp = 0, mfi = 0;
+    for (uint32_t c = tid; c < TC; c += BLOCK) {
+      const uint32_t v = s_aux[c];
+      mdp = (v >> 16) > mdp ? (v >> 16) : mdp;
+      mfi = (v & 0xFFFFu) > mfi ? (v & 0xFFFFu) : mfi;
+    }
+    mpk = block_max<NW>(mpk, s_tmp);
+    mfan = block_max<NW>(mfan, s_tmp);
+    mdp = block_max<NW>(mdp, s_tmp);
+    mfi = block_max<NW>(mfi, s_tmp);
+    if (tid == 0) {
+      if (stats) {
+        uint64_t *o = stats + (uint64_t)w * 8;
+        o[0] = n;
+        o[1] = TL;
+        o[2] = TR;
+        o[3] = TC;
+        o[4] = mpk;
+        o[5] = mfan;
+        o[6] = mdp;
+        o[7] = mfi;
+      }
+      if (win_nnz) win_nnz[w] = TL;
+    }
+    __syncthreads();  // LDS reused by the next window
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Hypersparse CSR to sorted COO (Sec. IV, "Data Representation": the
 // challenge's matrices come as CSR; the statistics here read the flat
 // entries). Row r (source address rows[r]) holds entries [row_ptr[r],
@@ -2119,6 +2324,16 @@ hipError_t launch_runs(const ScanShape &sh, int mode, const RunArgs &a, uint64_t
   if (sh.items == 8) return mode == 0 ? runs_impl<8, 0>(a, max_tiles, s) : runs_impl<8, 1>(a, max_tiles, s);
   if (sh.items == 16) return mode == 0 ? runs_impl<16, 0>(a, max_tiles, s) : runs_impl<16, 1>(a, max_tiles, s);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_small(const uint32_t *src, const uint32_t *dst, const uint64_t *off, uint32_t W,
+                        uint64_t *stats, uint64_t *win_keys, uint64_t *win_counts,
+                        uint64_t *win_nnz, hipStream_t s) {
+  if (W == 0) return hipSuccess;
+  const uint32_t grid = W < 2048u ? W : 2048u;
+  NS_LAUNCH(k_small, dim3(grid), dim3(kSmallBlock), s, src, dst, off, W, stats, win_keys,
+            win_counts, win_nnz);
+  return hipGetLastError();
 }
 
 hipError_t launch_segmax(const uint64_t *a, const uint64_t *b, const uint64_t *head_off,

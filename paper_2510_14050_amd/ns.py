@@ -78,7 +78,7 @@ EXPORTS = ("ns_workspace_size", "ns_build_matrix", "ns_accumulate_workspace_size
 # kernel kinds of ns_timing_read
 KINDS = ("fill", "tiles", "hist", "hist_scan", "pass0", "pass", "col_pass", "rle", "runs",
          "segmax", "finalize", "merge", "chunk_count", "pass0_chunked", "pass_chunked",
-         "col_pass_chunked")
+         "col_pass_chunked", "small")
 # default single-segment size from which sorts use the chunked passes
 # (ns_tuning_t.chunked_min = 0)
 CHUNKED_MIN_DEFAULT = 1 << 24

@@ -466,3 +466,56 @@ def test_workload_uneven1024_with_aggregate(gpu, bits):
     res = run_batch(torch, ns, src, dst, list(wl.sizes), agg=True, win=False,
                     tune=ns.tuning(digit_bits=bits, chunked_min=1 << 24))
     check_batch(ns, src, dst, *res)
+
+
+# Batches of at most 8192 packets in total run each window's whole pipeline in
+# one workgroup's LDS (k_small); one more packet takes the multi-kernel path.
+SMALL_BATCHES = {
+    "one_8192": [8192],
+    "one_8191": [8191],
+    "one_1": [1],
+    "empty_and_small": [0, 1, 0, 2, 17, 0],
+    "two_to_8192": [4096, 4096],
+    "sixteen": [512] * 15 + [512],
+    "ragged_8192": [3000, 1, 0, 2048, 2049, 1000, 94],
+    "ragged_8193": [3000, 1, 0, 2048, 2049, 1000, 95],
+    "many_empty": [0] * 300 + [8000] + [0] * 200,
+}
+
+
+@pytest.mark.parametrize("graph", [True, False])
+@pytest.mark.parametrize("name", sorted(SMALL_BATCHES))
+def test_small_batch_path(gpu, name, graph):
+    """Every window's quantities and matrix against the oracle, with and
+    without the aggregate, at and beyond the one-workgroup threshold."""
+    torch, ns = gpu
+    sizes = SMALL_BATCHES[name]
+    say("small batch", name, "graph" if graph else "eager")
+    src, dst = zipf_packets(300 + len(sizes), sum(sizes), pool=700)
+    for agg in (False, True):
+        res = run_batch(torch, ns, src, dst, sizes, graph=graph, agg=agg)
+        assert ns.device_status() == 0
+        check_batch(ns, src, dst, *res)
+
+
+@pytest.mark.parametrize("pattern", ["identical", "fan_out", "fan_in", "distinct", "two_rows"])
+def test_small_batch_extremes(gpu, pattern):
+    """Windows of 8192 packets whose counts, fan-out or fan-in reach 8192 (the
+    largest values the one-workgroup path packs into 16 bits)."""
+    torch, ns = gpu
+    n = 8192
+    i = np.arange(n, dtype=np.uint32)
+    if pattern == "identical":
+        src, dst = np.full(n, 7, np.uint32), np.full(n, 0xFFFFFFFF, np.uint32)
+    elif pattern == "fan_out":
+        src, dst = np.full(n, 0x80000000, np.uint32), (i * 2654435761).astype(np.uint32)
+    elif pattern == "fan_in":
+        src, dst = (i * 2654435761 + 1).astype(np.uint32), np.zeros(n, np.uint32)
+    elif pattern == "distinct":
+        src, dst = (i * 40503).astype(np.uint32), (i * 2654435761).astype(np.uint32)
+    else:
+        src, dst = (i & 1).astype(np.uint32), (i >> 1).astype(np.uint32)
+    say("small batch extremes", pattern)
+    res = run_batch(torch, ns, src, dst, [n], graph=False, agg=False)
+    assert ns.device_status() == 0
+    check_batch(ns, src, dst, *res)
