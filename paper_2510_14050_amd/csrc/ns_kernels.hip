@@ -631,8 +631,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const uint32_t shift = a.shift;
-  const uint64_t tiles = ld_const(a.tile_off + 1);
   const uint64_t seg_lo = ld_const(a.seg_off), seg_hi = ld_const(a.seg_off + 1);
+  const uint64_t tiles = (seg_hi - seg_lo + TILE - 1) / TILE;
   const uint32_t wbase = wv * (kWave * ITEMS);
 
   auto draw = [&]() {
