@@ -84,7 +84,7 @@ hipError_t launch_pass(const SortShape &sh, const PassArgs &a, uint64_t max_tile
 // --- batches of at most kSmallMax packets: the per-window pipeline of each
 // window inside one workgroup's LDS (quantities [W][8] and/or the positional
 // window matrices; null outputs are skipped) ---
-constexpr int kSmallBlock = 512;
+constexpr int kSmallBlock = 1024;
 constexpr uint32_t kSmallMax = 8192;  // packets per batch (so per window)
 hipError_t launch_small(const uint32_t *src, const uint32_t *dst, const uint64_t *off, uint32_t W,
                         uint64_t *stats, uint64_t *win_keys, uint64_t *win_counts,
