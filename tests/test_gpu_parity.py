@@ -58,7 +58,7 @@ def build_and_check(torch, ns, src, dst, ws=None):
 
 
 SIZES = [0, 1, 2, 7, 255, 256, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097,
-         8191, 8193, 12345, 65537, 131072]
+         8191, 8193, 12345, 16383, 16384, 16385, 65537, 131072]
 
 
 @pytest.mark.parametrize("n", SIZES)
@@ -498,10 +498,12 @@ def test_small_batch_path(gpu, name, graph):
         check_batch(ns, src, dst, *res)
 
 
-@pytest.mark.parametrize("pattern", ["identical", "fan_out", "fan_in", "distinct", "two_rows"])
+@pytest.mark.parametrize("pattern", ["identical", "fan_out", "fan_in", "distinct", "two_rows",
+                                     "blocks"])
 def test_small_batch_extremes(gpu, pattern):
     """Windows of 8192 packets whose counts, fan-out or fan-in reach 8192 (the
-    largest values the one-workgroup path packs into 16 bits)."""
+    largest values the one-workgroup path packs into 16 bits), and runs that
+    span a few threads' positions."""
     torch, ns = gpu
     n = 8192
     i = np.arange(n, dtype=np.uint32)
@@ -513,8 +515,10 @@ def test_small_batch_extremes(gpu, pattern):
         src, dst = (i * 2654435761 + 1).astype(np.uint32), np.zeros(n, np.uint32)
     elif pattern == "distinct":
         src, dst = (i * 40503).astype(np.uint32), (i * 2654435761).astype(np.uint32)
-    else:
+    elif pattern == "two_rows":
         src, dst = (i & 1).astype(np.uint32), (i >> 1).astype(np.uint32)
+    else:
+        src, dst = (i // 37).astype(np.uint32), ((i // 1000) * 77).astype(np.uint32)
     say("small batch extremes", pattern)
     res = run_batch(torch, ns, src, dst, [n], graph=False, agg=False)
     assert ns.device_status() == 0
