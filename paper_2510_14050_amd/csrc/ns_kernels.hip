@@ -143,71 +143,126 @@ __global__ __launch_bounds__(1024) void k_tiles(const uint64_t *seg_off, uint32_
 // p>=4 from src. Column items dst<<32|count: the 4 digits of dst. One launch
 // counts the four digits of one 32-bit array (dst, src, or the items' high
 // halves) into rows d0..d0+3 of each segment's histogram, so packets take two
-// launches that each read one array. Each workgroup takes a contiguous range
-// of tiles and counts into LDS; the counters go to the segment's global
-// histogram (one atomic per non-zero bin) only when the range crosses into the
-// next segment and at its end. Eight interleaved copies of the counters
-// (chosen by lane) spread the updates of a hot digit, which heavy-tailed
-// traffic produces in every wave, over eight addresses in different banks;
-// four digits at a time keep them within 32 KiB of LDS.
+// launches that each read one array (16-byte loads where the range allows).
+// Each workgroup takes a contiguous range of tiles and counts into LDS; the
+// counters go to the segment's global histogram (one atomic per non-zero bin)
+// when the range crosses into the next segment, at its end, and every
+// kHistFlushTiles tiles. The counters are the 16-bit halves of LDS words (the
+// two digits 2j and 2j+1 share word j) in 32 copies, and lane l updates copy
+// l % 32: whatever the digits, the 64 lanes of a wave hit every LDS bank
+// exactly twice, so a heavy-tailed digit costs no more than a uniform one.
+// Counting is bound by these LDS updates (four per value), not by the loads.
 // ---------------------------------------------------------------------------
+template <int BLOCK>
+struct HistShape {
+  static constexpr int kCopies = 32;
+  static constexpr int kRows = 4 * kBins / 2;  // counter words per copy
+  // most values one thread counts in a tile: its share of the 16-byte body,
+  // plus one value of the unaligned head and one of the tail
+  static constexpr uint32_t kPerThread = kHistTile / BLOCK + 2;
+  // most increments of one half-word per tile: two lanes per wave use a copy
+  static constexpr uint32_t kPerTile = 2 * (BLOCK / kWave) * kPerThread;
+  static constexpr uint32_t kFlushTiles = 65535 / kPerTile;
+  static_assert(kFlushTiles >= 1, "a tile could overflow a 16-bit counter");
+};
+
 template <int BLOCK, bool ITEMS64>
 __global__ __launch_bounds__(BLOCK) void k_hist(const uint32_t *__restrict__ vals,
                                                 const uint64_t *__restrict__ items,
                                                 const uint64_t *seg_off, const uint64_t *tile_off,
                                                 uint32_t W, uint32_t *hist, uint32_t row_stride,
                                                 uint32_t d0) {
-  constexpr int C = 8;
-  constexpr int NC = 4 * kBins;
-  __shared__ uint32_t s_h[NC * C];
+  using H = HistShape<BLOCK>;
+  constexpr int C = H::kCopies, ROWS = H::kRows;
+  __shared__ uint32_t s_h[ROWS * C];
   const uint64_t total = ld_const(tile_off + W);
   const uint64_t per = (total + gridDim.x - 1) / gridDim.x;
   const uint64_t t0 = (uint64_t)blockIdx.x * per, t1 = min(total, t0 + per);
   const uint32_t cp = threadIdx.x & (C - 1);
-  for (int i = threadIdx.x; i < NC * C; i += BLOCK) s_h[i] = 0;
+  for (int i = threadIdx.x; i < ROWS * C; i += BLOCK) s_h[i] = 0;
   __syncthreads();
-  // workgroups start their flush at different bins, so the ones that finish
-  // together do not queue on the same counters
-  const uint32_t rot = (blockIdx.x * BLOCK) % NC;
-  auto flush = [&](uint32_t w) {
-    uint32_t *g = hist + (uint64_t)w * row_stride + (uint64_t)d0 * kBins;
-    for (int i0 = threadIdx.x; i0 < NC; i0 += BLOCK) {
-      const int i = (i0 + rot) % NC;
-      uint32_t c = 0;
+  auto count = [&](uint32_t x) {
 #pragma unroll
-      for (int k = 0; k < C; ++k) {
-        c += s_h[i * C + k];
-        s_h[i * C + k] = 0;
-      }
-      if (c) atomicAdd(&g[i], c);
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t d = (x >> (8 * q)) & 255;
+      atomicAdd(&s_h[(q * (kBins / 2) + (d >> 1)) * C + cp], 1u << (16 * (d & 1)));
     }
   };
-  uint32_t cur = t0 < t1 ? find_owner_wave(tile_off, W, t0) : 0;
+  // workgroups start their flush at different rows, so the ones that finish
+  // together do not queue on the same global counters
+  const uint32_t rot = (blockIdx.x * 97u) % ROWS;
+  auto flush = [&](uint32_t w) {
+    uint32_t *g = hist + (uint64_t)w * row_stride + (uint64_t)d0 * kBins;
+    for (int r0 = threadIdx.x; r0 < ROWS; r0 += BLOCK) {
+      const int r = (r0 + rot) % ROWS;
+      uint32_t lo = 0, hi = 0;
+#pragma unroll 8
+      for (int k = 0; k < C; ++k) {
+        const int c = (k + r0) & (C - 1);  // neighbouring threads read different banks
+        const uint32_t x = s_h[r * C + c];
+        s_h[r * C + c] = 0;
+        lo += x & 0xFFFFu;
+        hi += x >> 16;
+      }
+      const int q = r / (kBins / 2), j = r % (kBins / 2);
+      if (lo) atomicAdd(&g[q * kBins + 2 * j], lo);
+      if (hi) atomicAdd(&g[q * kBins + 2 * j + 1], hi);
+    }
+  };
+  uint32_t cur = t0 < t1 ? find_owner_wave(tile_off, W, t0) : 0, since = 0;
   for (uint64_t t = t0; t < t1; ++t) {
     uint32_t w = cur;  // tiles come in order: step over finished (and empty) segments
     while (ld_const(tile_off + w + 1) <= t) ++w;
-    if (w != cur) {  // uniform: every thread sees the same tile
+    if (w != cur || since == H::kFlushTiles) {  // uniform: every thread sees the same tile
       __syncthreads();
       flush(cur);
       __syncthreads();
       cur = w;
+      since = 0;
     }
+    ++since;
     const uint64_t start = ld_const(seg_off + w) + (t - ld_const(tile_off + w)) * (uint64_t)kHistTile;
     const uint64_t end = min(start + (uint64_t)kHistTile, ld_const(seg_off + w + 1));
-    constexpr int R = 8;  // values per thread per round, loads issued together
-    for (uint64_t i0 = start + threadIdx.x; i0 < end; i0 += (uint64_t)R * BLOCK) {
-      uint32_t v[R];
+    if constexpr (ITEMS64) {
+      constexpr int R = 8;  // values per thread per round, loads issued together
+      for (uint64_t i0 = start + threadIdx.x; i0 < end; i0 += (uint64_t)R * BLOCK) {
+        uint32_t v[R];
 #pragma unroll
-      for (int k = 0; k < R; ++k) {
-        const uint64_t i = i0 + (uint64_t)k * BLOCK;
-        v[k] = i < end ? (ITEMS64 ? (uint32_t)(items[i] >> 32) : vals[i]) : 0;
+        for (int k = 0; k < R; ++k) {
+          const uint64_t i = i0 + (uint64_t)k * BLOCK;
+          v[k] = i < end ? (uint32_t)(items[i] >> 32) : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          if (i0 + (uint64_t)k * BLOCK >= end) break;
+          count(v[k]);
+        }
       }
+    } else {
+      // [a, b): the 16-byte aligned body; at most three values before and after
+      const uint64_t a =
+          min(end, start + ((4 - ((reinterpret_cast<uintptr_t>(vals + start) >> 2) & 3)) & 3));
+      const uint64_t b = a + ((end - a) & ~3ull);
+      if (threadIdx.x < a - start) count(vals[start + threadIdx.x]);
+      if (threadIdx.x < end - b) count(vals[b + threadIdx.x]);
+      const uint4 *v4 = reinterpret_cast<const uint4 *>(vals + a);
+      const uint64_t n4 = (b - a) / 4;
+      constexpr int R = kHistTile / (4 * BLOCK) > 0 ? kHistTile / (4 * BLOCK) : 1;
+      for (uint64_t j0 = threadIdx.x; j0 < n4; j0 += (uint64_t)R * BLOCK) {
+        uint4 x[R];
 #pragma unroll
-      for (int k = 0; k < R; ++k) {
-        if (i0 + (uint64_t)k * BLOCK >= end) break;
+        for (int k = 0; k < R; ++k) {
+          const uint64_t j = j0 + (uint64_t)k * BLOCK;
+          x[k] = j < n4 ? v4[j] : make_uint4(0, 0, 0, 0);
+        }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          atomicAdd(&s_h[(q * kBins + ((v[k] >> (8 * q)) & 255)) * C + cp], 1u);
+        for (int k = 0; k < R; ++k) {
+          if (j0 + (uint64_t)k * BLOCK >= n4) break;
+          count(x[k].x);
+          count(x[k].y);
+          count(x[k].z);
+          count(x[k].w);
+        }
       }
     }
   }
