@@ -1207,8 +1207,13 @@ constexpr int scan_waves() {
   return 160 / (KIB * ITEMS) < 6 ? 160 / (KIB * ITEMS) : 6;
 }
 
-template <int ITEMS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_waves<ITEMS, 4>())))
+// ROWS_LDS: row heads are staged in LDS and written by consecutive threads
+// (coalesced; for segments with many sources). Without it each thread writes
+// its own row heads straight from registers, which frees 4 B of LDS per key:
+// at 16 keys per thread a third workgroup fits on a CU, for one large segment
+// (where rows are few and the look-back's wait is what more workgroups hide).
+template <int ITEMS, bool ROWS_LDS = true>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_waves<ITEMS, ROWS_LDS || ITEMS < 16 ? 4 : 3>())))
 void k_rle(RleArgs a) {
   constexpr int BLOCK = 256;
   constexpr int TILE = BLOCK * ITEMS;
@@ -1216,8 +1221,8 @@ void k_rle(RleArgs a) {
   static_assert(TILE <= 65536, "tile positions are 16-bit");
   __shared__ uint64_t s_k[pd(TILE) + 1];  // s_k[pd(1 + i)] = key i of the tile
   __shared__ uint16_t s_hpos[TILE];   // link head positions in the tile
-  __shared__ uint16_t s_rpos[TILE];   // row head positions
-  __shared__ uint16_t s_rlr[TILE];    // tile-local link rank of each row head
+  __shared__ uint16_t s_rpos[ROWS_LDS ? TILE : 1];  // row head positions
+  __shared__ uint16_t s_rlr[ROWS_LDS ? TILE : 1];   // tile-local link rank of each row head
   __shared__ uint64_t s_tmp[BLOCK / kWave];
   __shared__ uint64_t s_L0, s_R0, s_trail, s_base;
   __shared__ uint32_t s_next, s_next_w;
@@ -1266,7 +1271,7 @@ void k_rle(RleArgs a) {
       uint32_t jl = xl, jr = xr;
 #pragma unroll
       for (int k = 0; k < ITEMS; ++k) {
-        if (rmask & (1u << k)) {
+        if (ROWS_LDS && (rmask & (1u << k))) {
           s_rpos[jr] = (uint16_t)(p0 + k);
           s_rlr[jr] = (uint16_t)jl;  // a row head is also a link head: its link rank
           ++jr;
@@ -1358,11 +1363,25 @@ void k_rle(RleArgs a) {
       }
       if (a.items) a.items[L] = (K << 32) | cnt;
     }
-    if (a.rpos) {
+    if (ROWS_LDS && a.rpos) {
       for (uint32_t q = tid; q < TR; q += BLOCK) {
         if (!in_bounds(R0 + q, a.lim + 2)) continue;
         a.rpos[R0 + q] = start + s_rpos[q];
         a.rlink[R0 + q] = L0 + s_rlr[q];
+      }
+    }
+    if (!ROWS_LDS && a.rpos && rmask) {  // each thread writes its own row heads
+      uint32_t q = xr;
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        if (rmask & (1u << k)) {
+          if (in_bounds(R0 + q, a.lim + 2)) {
+            a.rpos[R0 + q] = start + p0 + k;
+            // a row head is also a link head: its link index
+            a.rlink[R0 + q] = L0 + xl + __popc(lmask & ((1u << k) - 1u));
+          }
+          ++q;
+        }
       }
     }
     __syncthreads();
@@ -2346,19 +2365,24 @@ hipError_t launch_pass_chunked(const SortShape &sh, const PassArgs &a, const Chu
   return hipErrorInvalidValue;
 }
 
-template <int I>
+template <int I, bool ROWS_LDS = true>
 static hipError_t rle_impl(const RleArgs &a, uint64_t max_tiles, hipStream_t s) {
   static uint64_t cap[64];
   const int d = device_id();
-  if (!cap[d]) cap[d] = resident(k_rle<I>, 256);
-  NS_LAUNCH(k_rle<I>, dim3(clamp_grid(max_tiles, cap[d])), dim3(256), s, a);
+  if (!cap[d]) cap[d] = resident(k_rle<I, ROWS_LDS>, 256);
+  NS_LAUNCH((k_rle<I, ROWS_LDS>), dim3(clamp_grid(max_tiles, cap[d])), dim3(256), s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_rle(const ScanShape &sh, const RleArgs &a, uint64_t max_tiles, hipStream_t s) {
   if (sh.items == 4) return rle_impl<4>(a, max_tiles, s);
   if (sh.items == 8) return rle_impl<8>(a, max_tiles, s);
-  if (sh.items == 16) return rle_impl<16>(a, max_tiles, s);
+  if (sh.items == 16) {
+    // one segment of 2^24 keys or more: 3 workgroups per CU, rows from registers
+    // (2^30 keys: 4.77 vs 4.98 ms; 8192 windows of 2^17 keys lose, 7.5 vs 6.0 ms)
+    if (a.W == 1 && max_tiles * 256 * 16 >= (1ull << 24)) return rle_impl<16, false>(a, max_tiles, s);
+    return rle_impl<16>(a, max_tiles, s);
+  }
   return hipErrorInvalidValue;
 }
 
