@@ -477,6 +477,7 @@ SMALL_BATCHES = {
     "empty_and_small": [0, 1, 0, 2, 17, 0],
     "two_to_8192": [4096, 4096],
     "sixteen": [512] * 15 + [512],
+    "four_2000": [2000] * 4,
     "ragged_8192": [3000, 1, 0, 2048, 2049, 1000, 94],
     "ragged_8193": [3000, 1, 0, 2048, 2049, 1000, 95],
     "many_empty": [0] * 300 + [8000] + [0] * 200,
@@ -498,14 +499,15 @@ def test_small_batch_path(gpu, name, graph):
         check_batch(ns, src, dst, *res)
 
 
+@pytest.mark.parametrize("n", [8192, 8193])
 @pytest.mark.parametrize("pattern", ["identical", "fan_out", "fan_in", "distinct", "two_rows",
-                                     "blocks"])
-def test_small_batch_extremes(gpu, pattern):
+                                     "blocks", "all_ones"])
+def test_small_batch_extremes(gpu, pattern, n):
     """Windows of 8192 packets whose counts, fan-out or fan-in reach 8192 (the
-    largest values the one-workgroup path packs into 16 bits), and runs that
-    span a few threads' positions."""
+    largest values the one-workgroup path packs into 16 bits), runs that span
+    a few threads' positions, and the all-ones key; the same patterns one
+    packet over, on the multi-kernel path."""
     torch, ns = gpu
-    n = 8192
     i = np.arange(n, dtype=np.uint32)
     if pattern == "identical":
         src, dst = np.full(n, 7, np.uint32), np.full(n, 0xFFFFFFFF, np.uint32)
@@ -517,8 +519,11 @@ def test_small_batch_extremes(gpu, pattern):
         src, dst = (i * 40503).astype(np.uint32), (i * 2654435761).astype(np.uint32)
     elif pattern == "two_rows":
         src, dst = (i & 1).astype(np.uint32), (i >> 1).astype(np.uint32)
-    else:
+    elif pattern == "blocks":
         src, dst = (i // 37).astype(np.uint32), ((i // 1000) * 77).astype(np.uint32)
+    else:  # a third of the packets on the all-ones key, the rest spread below it
+        src = np.where(i % 3 == 0, 0xFFFFFFFF, i * 2654435761).astype(np.uint32)
+        dst = np.where(i % 3 == 0, 0xFFFFFFFF, i // 5).astype(np.uint32)
     say("small batch extremes", pattern)
     res = run_batch(torch, ns, src, dst, [n], graph=False, agg=False)
     assert ns.device_status() == 0
