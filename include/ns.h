@@ -280,6 +280,13 @@ int ns_rolling_update(const ns_rolling_t *r, const ns_matrix_t *add, const ns_ma
 /* Copies the live entries of `from` into `to` (same slot counts), dropping the
  * tombstones of links, sources and destinations whose counts returned to 0. */
 int ns_rolling_compact(const ns_rolling_t *from, const ns_rolling_t *to, void *stream);
+/* Writes to slots_used[0..2] (device, 3 x uint64) the slots taken in the link,
+ * source and destination tables since the last ns_rolling_init or since the
+ * state was filled by ns_rolling_compact: live entries plus tombstones, the
+ * occupancy that decides when to compact (the link key 0xFFFFFFFFFFFFFFFF is
+ * kept outside the table and not counted). Enqueued on `stream` after the
+ * state's earlier calls. */
+int ns_rolling_occupancy(const ns_rolling_t *r, uint64_t *slots_used, void *stream);
 
 /* Synchronises `stream`, then reads and clears the current device's error
  * word: *status (host) = NS_OK, NS_ERR_BOUNDS (an index outside its array; the

@@ -1216,6 +1216,15 @@ int ns_rolling_compact(const ns_rolling_t *from, const ns_rolling_t *to, void *s
   return NS_OK;
 }
 
+int ns_rolling_occupancy(const ns_rolling_t *r, uint64_t *slots_used, void *stream) {
+  int rc = rolling_check(r);
+  if (rc) return rc;
+  if (!slots_used) return NS_ERR_INVALID_ARG;
+  const RollTables t = roll_tables(r->mem, r->link_slots, r->address_slots);
+  HIP_TRY(launch_roll_used(t, slots_used, static_cast<hipStream_t>(stream)));
+  return NS_OK;
+}
+
 int ns_device_status(void *stream, int *status) {
   if (!status) return NS_ERR_INVALID_ARG;
   HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));

@@ -216,6 +216,8 @@ hipError_t launch_check_total(const uint64_t *stats, uint64_t packets, hipStream
 struct RollHeader {
   uint64_t links, sources, dests, packets;  // live counts
   uint64_t scan[4];                         // maxima found by the last scan
+  uint64_t used[3];                         // slots taken since the last clear or compaction
+                                            // (link, source, destination tables)
   uint32_t special_count;                   // count of the link key 0xFFFFFFFFFFFFFFFF
   uint32_t pad;
 };
@@ -242,6 +244,7 @@ hipError_t launch_roll_update(const RollTables &t, const RollDelta &d, uint64_t 
                               hipStream_t s);
 hipError_t launch_roll_stats(const RollTables &t, uint64_t *out, hipStream_t s);
 hipError_t launch_roll_compact(const RollTables &from, const RollTables &to, hipStream_t s);
+hipError_t launch_roll_used(const RollTables &t, uint64_t *out, hipStream_t s);
 
 // device error word: bit 0 underflow, bit 1 capacity (hash table full), bit 2
 // invalid input, bit 3 an index outside its array (bounds-checked builds)

@@ -10,7 +10,9 @@
 // Open addressing with linear probing; keys are never removed (an entry whose
 // count drops to zero stays as a tombstone that only its own key reuses), so a
 // lookup never meets an empty slot before its key. Compaction into a fresh
-// state drops the tombstones.
+// state drops the tombstones. The header counts the slots taken in each table
+// since the last clear or compaction (live entries plus tombstones), which is
+// what decides when to compact.
 //
 // The eight quantities follow from the tables: a link appears when its count
 // leaves zero and disappears when it returns to zero (unique links, fan-out of
@@ -43,9 +45,10 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t z) {
 __device__ __forceinline__ uint64_t ld64(const uint64_t *p) { return lb_load(p); }
 
 // slot of `key` in a table of `cap` (power of two) u64 keys, inserting it if
-// absent; `empty` marks a free slot. Returns cap on overflow.
+// absent; `empty` marks a free slot; *took is set when this call took a free
+// slot. Returns cap on overflow.
 __device__ uint64_t find_or_insert(uint64_t *keys, uint64_t cap, uint64_t key, uint64_t empty,
-                                   bool insert) {
+                                   bool insert, bool *took) {
   uint64_t i = fmix64(key) & (cap - 1);
   for (uint32_t probe = 0; probe < kProbeLimit; ++probe) {
     const uint64_t cur = ld64(keys + i);
@@ -54,6 +57,7 @@ __device__ uint64_t find_or_insert(uint64_t *keys, uint64_t cap, uint64_t key, u
       if (!insert) return cap;
       const uint64_t prev = atomicCAS((unsigned long long *)(keys + i), (unsigned long long)empty,
                                       (unsigned long long)key);
+      if (prev == empty) *took = true;
       if (prev == empty || prev == key) return i;
     }
     i = (i + 1) & (cap - 1);
@@ -64,17 +68,19 @@ __device__ uint64_t find_or_insert(uint64_t *keys, uint64_t cap, uint64_t key, u
 __device__ __forceinline__ void flag_status(int bit) { atomicOr(&g_status, bit); }
 
 // one address side (source or destination): packets +-c, fan +-1 on link
-// appearance / disappearance; presence transitions update the live count
-__device__ void address_update(const RollTables &t, bool src_side, uint32_t addr, uint32_t dp,
-                               bool plus, int dfan) {
+// appearance / disappearance; presence transitions update the live count.
+// Returns 1 when the address took a free slot.
+__device__ uint32_t address_update(const RollTables &t, bool src_side, uint32_t addr, uint32_t dp,
+                                   bool plus, int dfan) {
   uint64_t *keys = src_side ? t.src_keys : t.dst_keys;
   uint32_t *pk = src_side ? t.src_pk : t.dst_pk;
   uint32_t *fan = src_side ? t.src_fan : t.dst_fan;
   unsigned long long *live = (unsigned long long *)(src_side ? &t.hdr->sources : &t.hdr->dests);
-  const uint64_t s = find_or_insert(keys, t.addr_cap, (uint64_t)addr + 1, 0, plus);
+  bool took = false;
+  const uint64_t s = find_or_insert(keys, t.addr_cap, (uint64_t)addr + 1, 0, plus, &took);
   if (s == t.addr_cap) {
     flag_status(plus ? 2 : 1);
-    return;
+    return 0;
   }
   if (plus) {
     const uint32_t old = atomicAdd(pk + s, dp);
@@ -87,12 +93,14 @@ __device__ void address_update(const RollTables &t, bool src_side, uint32_t addr
   }
   if (dfan > 0) atomicAdd(fan + s, 1u);
   if (dfan < 0) atomicSub(fan + s, 1u);
+  return took ? 1u : 0u;
 }
 
 __global__ __launch_bounds__(256) void k_roll_update(RollTables t, RollDelta d) {
   const uint64_t na = d.add_nnz ? min(*d.add_nnz, d.add_cap) : 0;
   const uint64_t nr = d.rem_nnz ? min(*d.rem_nnz, d.rem_cap) : 0;
   if (blockIdx.x == 0 && threadIdx.x < 4) t.hdr->scan[threadIdx.x] = 0;  // for the scan that follows
+  uint32_t took[3] = {0, 0, 0};  // slots this thread took (links, sources, destinations)
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < na + nr;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const bool plus = i < na;
@@ -102,11 +110,13 @@ __global__ __launch_bounds__(256) void k_roll_update(RollTables t, RollDelta d) 
     if (key == kEmptyLink) {
       cnt = &t.hdr->special_count;
     } else {
-      const uint64_t s = find_or_insert(t.link_keys, t.link_cap, key, kEmptyLink, plus);
+      bool tk = false;
+      const uint64_t s = find_or_insert(t.link_keys, t.link_cap, key, kEmptyLink, plus, &tk);
       if (s == t.link_cap) {
         flag_status(plus ? 2 : 1);
         continue;
       }
+      took[0] += tk;
       cnt = t.link_cnt + s;
     }
     int dfan = 0;
@@ -130,8 +140,15 @@ __global__ __launch_bounds__(256) void k_roll_update(RollTables t, RollDelta d) 
         dfan = -1;
       }
     }
-    address_update(t, true, (uint32_t)(key >> 32), c, plus, dfan);
-    address_update(t, false, (uint32_t)key, c, plus, dfan);
+    took[1] += address_update(t, true, (uint32_t)(key >> 32), c, plus, dfan);
+    took[2] += address_update(t, false, (uint32_t)key, c, plus, dfan);
+  }
+  // one counter update per wave and table (a counter hit by every insert
+  // would serialise them)
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const uint64_t w = wave_sum((uint64_t)took[q]);
+    if ((threadIdx.x & (kWave - 1)) == 0 && w) atomicAdd((unsigned long long *)&t.hdr->used[q], w);
   }
 }
 
@@ -194,6 +211,7 @@ __global__ __launch_bounds__(256) void k_roll_clear(RollTables t) {
     h->links = h->sources = h->dests = h->packets = 0;
     h->special_count = 0;
     for (int q = 0; q < 4; ++q) h->scan[q] = 0;
+    for (int q = 0; q < 3; ++q) h->used[q] = 0;
   }
 }
 
@@ -204,13 +222,15 @@ __global__ __launch_bounds__(256) void k_roll_compact(RollTables from, RollTable
   for (uint64_t i = i0; i < from.link_cap; i += stride) {
     const uint32_t c = from.link_cnt[i];
     if (!c) continue;
-    const uint64_t s = find_or_insert(to.link_keys, to.link_cap, from.link_keys[i], kEmptyLink, true);
+    bool tk = false;  // not needed here: the live counts give the slots taken
+    const uint64_t s = find_or_insert(to.link_keys, to.link_cap, from.link_keys[i], kEmptyLink, true, &tk);
     if (s == to.link_cap) flag_status(2);
     else to.link_cnt[s] = c;
   }
   for (uint64_t i = i0; i < from.addr_cap; i += stride) {
     if (from.src_pk[i]) {
-      const uint64_t s = find_or_insert(to.src_keys, to.addr_cap, from.src_keys[i], 0, true);
+      bool tk = false;
+      const uint64_t s = find_or_insert(to.src_keys, to.addr_cap, from.src_keys[i], 0, true, &tk);
       if (s == to.addr_cap) flag_status(2);
       else {
         to.src_pk[s] = from.src_pk[i];
@@ -218,7 +238,8 @@ __global__ __launch_bounds__(256) void k_roll_compact(RollTables from, RollTable
       }
     }
     if (from.dst_pk[i]) {
-      const uint64_t s = find_or_insert(to.dst_keys, to.addr_cap, from.dst_keys[i], 0, true);
+      bool tk = false;
+      const uint64_t s = find_or_insert(to.dst_keys, to.addr_cap, from.dst_keys[i], 0, true, &tk);
       if (s == to.addr_cap) flag_status(2);
       else {
         to.dst_pk[s] = from.dst_pk[i];
@@ -232,7 +253,17 @@ __global__ __launch_bounds__(256) void k_roll_compact(RollTables from, RollTable
     to.hdr->dests = from.hdr->dests;
     to.hdr->packets = from.hdr->packets;
     to.hdr->special_count = from.hdr->special_count;
+    // the new tables hold the live entries only (the all-ones link lives outside)
+    to.hdr->used[0] = from.hdr->links - (from.hdr->special_count ? 1 : 0);
+    to.hdr->used[1] = from.hdr->sources;
+    to.hdr->used[2] = from.hdr->dests;
   }
+}
+
+// slots taken in the link, source and destination tables since the last
+// clear or compaction
+__global__ void k_roll_used(RollTables t, uint64_t *out) {
+  if (threadIdx.x < 3) out[threadIdx.x] = t.hdr->used[threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -300,6 +331,11 @@ hipError_t launch_roll_compact(const RollTables &from, const RollTables &to, hip
   hipError_t e = launch_roll_clear(to, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_roll_compact, dim3(grid_for(from.link_cap)), dim3(256), 0, s, from, to);
+  return hipGetLastError();
+}
+
+hipError_t launch_roll_used(const RollTables &t, uint64_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_roll_used, dim3(1), dim3(64), 0, s, t, out);
   return hipGetLastError();
 }
 

@@ -71,7 +71,8 @@ EXPORTS = ("ns_workspace_size", "ns_build_matrix", "ns_accumulate_workspace_size
            "ns_stats_csr_workspace_size", "ns_stats_csr",
            "ns_batch_stats", "ns_batch_stats_eager", "ns_max_link_packets",
            "ns_batch_max_link_packets", "ns_rolling_size", "ns_rolling_init",
-           "ns_rolling_update", "ns_rolling_compact", "ns_device_status", "ns_release_graphs",
+           "ns_rolling_update", "ns_rolling_compact", "ns_rolling_occupancy",
+           "ns_device_status", "ns_release_graphs",
            "ns_timing_enable", "ns_timing_reset", "ns_timing_read",
            "ns_error_string", "ns_version")
 
@@ -119,6 +120,7 @@ def load(path: str = LIB_PATH):
     lib.ns_rolling_init.argtypes = [PR, P]
     lib.ns_rolling_update.argtypes = [PR, PM, PM, P, P]
     lib.ns_rolling_compact.argtypes = [PR, PR, P]
+    lib.ns_rolling_occupancy.argtypes = [PR, P, P]
     lib.ns_device_status.argtypes = [P, ctypes.POINTER(I)]
     lib.ns_release_graphs.argtypes = []
     lib.ns_timing_enable.argtypes = [I]
@@ -484,6 +486,15 @@ def rolling_compact(src: RollingState, dst: RollingState, stream=None):
     a, b = src.view(), dst.view()
     _check(load().ns_rolling_compact(ctypes.byref(a), ctypes.byref(b), _stream(stream)),
            "ns_rolling_compact")
+
+
+def rolling_occupancy(state: RollingState, out, stream=None):
+    """Slots taken in the link, source and destination tables since the last
+    clear or compaction, into out (3 int64, device)."""
+    v = state.view()
+    _check(load().ns_rolling_occupancy(ctypes.byref(v), _ptr(out), _stream(stream)),
+           "ns_rolling_occupancy")
+    return out
 
 
 def device_status(stream=None) -> int:

@@ -180,6 +180,9 @@ class Server:
         self.roll_dev = torch.zeros((self.slots, 8), dtype=torch.int64, device=d)
         self.win_host = torch.zeros((self.slots, 8), dtype=torch.int64).pin_memory()
         self.roll_host = torch.zeros((self.slots, 8), dtype=torch.int64).pin_memory()
+        # slots taken in the rolling state's link / source / destination tables
+        self.occ_dev = torch.zeros((self.slots, 3), dtype=torch.int64, device=d)
+        self.occ_host = torch.zeros((self.slots, 3), dtype=torch.int64).pin_memory()
         self.bslots = self.slots            # per-batch offsets / nnz rows
         self.pin_off = torch.zeros((self.bslots, max_batch + 1), dtype=torch.int64).pin_memory()
         self.off_dev = torch.zeros((self.bslots, max_batch + 1), dtype=torch.int64, device=d)
@@ -306,6 +309,8 @@ class Server:
                 else:
                     ns.rolling_update(self.states[st.si], win, old, self.roll_dev[k])
                     self._maybe_compact(st, seq)
+                    ns.rolling_occupancy(self.states[st.si], self.occ_dev[k])
+                    self.occ_host[k].copy_(self.occ_dev[k], non_blocking=True)
                 if old is not None and last_of_batch:  # its whole matrix region can go
                     ev = torch.cuda.Event()
                     ev.record(self.s_roll)
@@ -323,35 +328,33 @@ class Server:
 
     def _maybe_compact(self, st, seq: int):
         """Move the rolling state into the other buffer, dropping tombstones, once
-        the slots possibly occupied in a table (live entries at the last
-        compaction plus one per packet added since) could pass 60% of it. Live
-        entries are bounded by the counts of the latest arrival already on the
-        host plus one per packet added after it, and by the packets in the ring;
-        when that bound exceeds half a table, the exact counts of this update
-        are read (one synchronisation) before the state is declared too small."""
-        n = int(st.sizes[seq])
-        st.occ = [o + n for o in st.occ]
+        the slots taken in one of its tables (live entries plus tombstones, which
+        the device counts) could pass 60% of it: the counts of the latest arrival
+        the host has seen plus one per packet added since (a packet takes at most
+        one new slot per table). Live entries are bounded the same way (and by
+        the packets in the ring); only when that bound passes half a table are
+        this update's exact counts read (one synchronisation) before the state is
+        declared too small."""
         caps = (self.link_slots, self.address_slots, self.address_slots)
-        if all(o <= 0.6 * c for o, c in zip(st.occ, caps)):
-            return
-        kseq, known = st.known
+        kseq, used, live = st.known
         added = int(st.csum[seq + 1] - st.csum[kseq + 1]) if kseq >= 0 else int(st.csum[seq + 1])
+        if all(u + added <= 0.6 * c for u, c in zip(used, caps)):
+            return
         in_ring = int(st.csum[seq + 1] - st.csum[max(0, seq + 1 - self.ring)])
-        live = [min(k + added, in_ring) for k in known]
+        live = tuple(min(lv + added, in_ring) for lv in live)
         if any(lv > 0.5 * c for lv, c in zip(live, caps)):
             # the bound is loose when the host has not seen a recent result:
             # wait for this update and take its exact counts
             self.s_roll.synchronize()
             rs = self.roll_dev[seq % self.slots].cpu()
-            live = [int(rs[1]), int(rs[2]), int(rs[3])]
-            st.known = (seq, tuple(live))
+            live = (int(rs[1]), int(rs[2]), int(rs[3]))
             if any(lv > 0.5 * c for lv, c in zip(live, caps)):
                 raise RuntimeError("rolling aggregate outgrows its hash tables; "
                                    "raise the slot counts")
         nxt = 1 - st.si
         ns.rolling_compact(self.states[st.si], self.states[nxt])
         st.si = nxt
-        st.occ = live
+        st.known = (seq, live, live)  # the new tables hold the live entries only
         st.compactions += 1
 
     def _accumulate(self, st, cur, win, sign):
@@ -380,8 +383,9 @@ class Server:
         st.cur, st.prev = self.empty, None
         st.timed = []
         st.si, st.compactions = 0, 0
-        st.occ = [0, 0, 0]             # possibly occupied link / source / destination slots
-        st.known = (-1, (0, 0, 0))     # (seq, (links, sources, destinations)) seen on the host
+        # latest counts on the host: (seq, slots taken per table, live links /
+        # sources / destinations)
+        st.known = (-1, (0, 0, 0), (0, 0, 0))
         st.sizes = np.array([w[0].size for w in windows], np.int64)
         st.csum = np.concatenate([[0], np.cumsum(st.sizes)])
         if self.mode == "hash":
@@ -419,9 +423,10 @@ class Server:
                                       self.win_host[k].numpy().view(np.uint64).copy(),
                                       self.roll_host[k].numpy().view(np.uint64).copy(),
                                       t_arr, t, bidx)
-                rs = results[seq].rolling_stats
-                if seq > st.known[0]:
-                    st.known = (seq, (int(rs[1]), int(rs[2]), int(rs[3])))
+                if self.mode == "hash" and seq > st.known[0]:
+                    u, rs = self.occ_host[k], results[seq].rolling_stats
+                    st.known = (seq, (int(u[0]), int(u[1]), int(u[2])),
+                                (int(rs[1]), int(rs[2]), int(rs[3])))
                 done_q.popleft()
                 completed[0] += 1
 

@@ -44,17 +44,32 @@ def test_rolling_matches_oracle(link_slots, addr_slots):
     states = [ns.RollingState(link_slots, addr_slots), ns.RollingState(link_slots, addr_slots)]
     cur = 0
     out = torch.zeros(8, dtype=torch.int64, device="cuda")
+    occ = torch.zeros(3, dtype=torch.int64, device="cuda")
+    ones = (1 << 64) - 1  # the all-ones link is counted outside the table
+
+    def keys(j):
+        s, d = wins[j]
+        return set(((s.astype(np.uint64) << np.uint64(32)) | d.astype(np.uint64)).tolist()) - {ones}
+    taken = [set(), set(), set()]  # keys that took a slot since the clear / compaction
     for k in range(len(wins)):
         old = mats[k - ring] if k >= ring else None
         ns.rolling_update(states[cur], mats[k], old, out)
+        taken[0] |= keys(k)
+        taken[1] |= set(wins[k][0].tolist())
+        taken[2] |= set(wins[k][1].tolist())
+        lo = max(0, k - ring + 1)
         if k % 7 == 6:  # compaction keeps everything
             ns.rolling_compact(states[cur], states[1 - cur])
             cur = 1 - cur
+            taken = [set().union(*(keys(j) for j in range(lo, k + 1))),
+                     set(np.concatenate([wins[j][0] for j in range(lo, k + 1)]).tolist()),
+                     set(np.concatenate([wins[j][1] for j in range(lo, k + 1)]).tolist())]
+        ns.rolling_occupancy(states[cur], occ)
         torch.cuda.synchronize()
-        lo = max(0, k - ring + 1)
         want = oracle.stats(np.concatenate([wins[j][0] for j in range(lo, k + 1)]),
                             np.concatenate([wins[j][1] for j in range(lo, k + 1)]))
         assert ns.stats_numpy(out).tolist() == want.tolist(), k
+        assert occ.cpu().tolist() == [len(t) for t in taken], k
     assert ns.device_status() == 0
     # remove everything that is left: the empty aggregate
     for k in range(len(wins) - ring, len(wins)):
