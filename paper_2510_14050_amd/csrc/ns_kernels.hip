@@ -803,7 +803,7 @@ __device__ __forceinline__ void chunk_geometry(const ChunkArgs &c, uint32_t tile
 
 template <int BLOCK, bool PACKETS, int R>
 __global__ __launch_bounds__(BLOCK) void k_chunk_hist(PassArgs a, ChunkArgs c, uint32_t tile) {
-  constexpr int C = 4;  // interleaved counter copies (see k_hist_packets)
+  constexpr int C = 4;  // counter copies chosen by lane: a hot digit spreads over four
   constexpr uint32_t B = 1u << R;
   __shared__ uint32_t s_h[B * C];
   uint64_t lo, n, tiles, per;
