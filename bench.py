@@ -212,7 +212,7 @@ def bytes_model(N, W, got, got_agg, per_window, aggregate, cmin, bits):
     return total
 
 
-def survey_bytes(N, links):
+def sort_model_bytes(N, links):
     """The sort-method model of the method's algorithmic bytes with byte digits
     (8 key passes, 4 column passes): M = 16 + 16*8 + r*(76 + 24*4) bytes per
     packet, r = links / packets."""
@@ -265,7 +265,7 @@ def path_rates(workload, N, W, got, got_agg, ms_step, per_window, aggregate, cmi
     sec = ms_step * 1e-3
     M = bytes_model(N, W, got, got_agg, per_window, aggregate, cmin, bits)
     links = int(got_agg[1]) if aggregate else int(got[:, 1].sum())
-    S = survey_bytes(N, links)
+    S = sort_model_bytes(N, links)
     F = 8 * N + 64 * (W if per_window else 1)
     out = {"step_ms": round(ms_step, 4), "peak_gbs": PEAK_HBM_GBS,
            "model_bytes": M, "model_bytes_per_packet": round(M / max(N, 1), 2),
