@@ -354,7 +354,8 @@ class Server:
         nxt = 1 - st.si
         ns.rolling_compact(self.states[st.si], self.states[nxt])
         st.si = nxt
-        st.known = (seq, live, live)  # the new tables hold the live entries only
+        with st.known_lock:  # the completer thread updates it too
+            st.known = (seq, live, live)  # the new tables hold the live entries only
         st.compactions += 1
 
     def _accumulate(self, st, cur, win, sign):
@@ -386,6 +387,7 @@ class Server:
         # latest counts on the host: (seq, slots taken per table, live links /
         # sources / destinations)
         st.known = (-1, (0, 0, 0), (0, 0, 0))
+        st.known_lock = threading.Lock()
         st.sizes = np.array([w[0].size for w in windows], np.int64)
         st.csum = np.concatenate([[0], np.cumsum(st.sizes)])
         if self.mode == "hash":
@@ -423,10 +425,12 @@ class Server:
                                       self.win_host[k].numpy().view(np.uint64).copy(),
                                       self.roll_host[k].numpy().view(np.uint64).copy(),
                                       t_arr, t, bidx)
-                if self.mode == "hash" and seq > st.known[0]:
+                if self.mode == "hash":
                     u, rs = self.occ_host[k], results[seq].rolling_stats
-                    st.known = (seq, (int(u[0]), int(u[1]), int(u[2])),
-                                (int(rs[1]), int(rs[2]), int(rs[3])))
+                    with st.known_lock:  # never replace a later count (a compaction's)
+                        if seq > st.known[0]:
+                            st.known = (seq, (int(u[0]), int(u[1]), int(u[2])),
+                                        (int(rs[1]), int(rs[2]), int(rs[3])))
                 done_q.popleft()
                 completed[0] += 1
 

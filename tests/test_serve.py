@@ -78,6 +78,7 @@ def _compaction_setup(monkeypatch, live, known, sizes):
     CPU: 1000 link slots and 1000 address slots, a ring of 64 arrivals;
     `known` = (seq, slots taken, live counts) last seen on the host, `live` =
     this update's exact live counts."""
+    import threading
     import types
 
     import torch
@@ -88,7 +89,7 @@ def _compaction_setup(monkeypatch, live, known, sizes):
     srv = types.SimpleNamespace(link_slots=1000, address_slots=1000, ring=64, slots=8,
                                 s_roll=_Stream(), states=["state0", "state1"],
                                 roll_dev=torch.zeros((8, 8), dtype=torch.int64))
-    st = types.SimpleNamespace(si=0, compactions=0, known=known,
+    st = types.SimpleNamespace(si=0, compactions=0, known=known, known_lock=threading.Lock(),
                                sizes=np.array(sizes, np.int64))
     st.csum = np.concatenate([[0], np.cumsum(st.sizes)])
     seq = len(sizes) - 1
