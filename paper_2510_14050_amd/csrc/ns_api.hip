@@ -248,7 +248,7 @@ int resolve_tuning(const ns_tuning_t *t, Shapes *sh) {
 // ... ends in items_in).
 int enqueue_columns(Ws &ws, const Shapes &sh, uint64_t *items, uint64_t *tmp,
                     const uint64_t *link_off, uint32_t W, uint64_t max_items, uint64_t *stats,
-                    hipStream_t s, const uint64_t *gather = nullptr) {
+                    hipStream_t s, const uint64_t *gather = nullptr, uint64_t packets = 0) {
   const Layout &L = ws.L;
   uint64_t *t_csort = ws.at<uint64_t>(L.t_csort), *t_run = ws.at<uint64_t>(L.t_run);
   uint32_t *chist = ws.at<uint32_t>(L.chist), *cbase = ws.at<uint32_t>(L.cbase);
@@ -319,6 +319,7 @@ int enqueue_columns(Ws &ws, const Shapes &sh, uint64_t *items, uint64_t *tmp,
   r.wide = gather != nullptr;  // items carry link indices; counts come from `gather`
   r.gather = gather;
   r.lim = max_items;
+  r.vlim = packets;  // the items' counts sum to the packets
   HIP_TRY(timed(K_RUNS, s, [&] { return launch_runs(sh.scan, 1, r, run_tiles, s); }));
   // fan-in = run length, destination packets = run sum
   HIP_TRY(timed(K_SEGMAX, s, [&] { return launch_segmax(hpos, hval, col_off, W, max_items, stats, 7, 6, s); }));
@@ -457,7 +458,7 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
   HIP_TRY(timed(K_SEGMAX, s, [&] { return launch_segmax(rpos, rlink, row_off, W, N, o.stats, 4, 5, s); }));
   // columns: items are sorted in place (ping-pong with the other sort buffer)
   uint64_t *tmp = (items == ws.at<uint64_t>(L.KA)) ? ws.at<uint64_t>(L.KB) : ws.at<uint64_t>(L.KA);
-  int rc = enqueue_columns(ws, sh, items, tmp, link_off, W, N, o.stats, s);
+  int rc = enqueue_columns(ws, sh, items, tmp, link_off, W, N, o.stats, s, nullptr, N);
   if (rc) return rc;
   HIP_TRY(timed(K_FINAL, s, [&] { return launch_finalize(seg_off, link_off, row_off, ws.at<uint64_t>(L.col_off), W, o.stats, s); }));
   return NS_OK;
@@ -506,13 +507,14 @@ int enqueue_matrix_stats(Ws &ws, const Shapes &sh, const ns_matrix_t *m, uint64_
   r.ticket = ws.ticket();
   r.wide = wide;
   r.lim = cap;
+  r.vlim = m->packets;
   HIP_TRY(timed(K_RUNS, s, [&] { return launch_runs(sh.scan, 0, r, run_tiles, s); }));
   // fan-out = run length, source packets = run sum
   HIP_TRY(timed(K_SEGMAX, s, [&] { return launch_segmax(hpos, hval, row_off, 1, cap, stats, 5, 4, s); }));
   // valid packets = value sentinel, read before the column pass reuses hpos/hval
   HIP_TRY(timed(K_FINAL, s, [&] { return launch_finalize_matrix(hval, row_off, nullptr, m->nnz, stats, s); }));
   int rc = enqueue_columns(ws, sh, items, tmp, link_off, 1, cap, stats, s,
-                           wide ? m->counts : nullptr);
+                           wide ? m->counts : nullptr, m->packets);
   if (rc) return rc;
   HIP_TRY(timed(K_FINAL, s, [&] { return launch_finalize_matrix(nullptr, nullptr, ws.at<uint64_t>(L.col_off), nullptr, stats, s); }));
   return NS_OK;

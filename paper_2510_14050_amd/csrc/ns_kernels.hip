@@ -1458,6 +1458,8 @@ void k_runs(RunArgs a) {
 
   const int tid = threadIdx.x, wv = tid / kWave;
   const uint64_t total = ld_const(a.tile_off + a.W);
+  // heads and values in one look-back word per tile when both sums stay below 2^31
+  const bool packed = !WIDE && a.lim < (1ull << 31) && a.vlim && a.vlim < (1ull << 31);
   if (wv == 3) claim_tile(a.ticket, a.tile_off, a.W, total, &s_next, &s_next_w);
   __syncthreads();
   ScanTile g = scan_tile(a.tile_off, a.seg_off, s_next, s_next_w, total, TILE);
@@ -1540,16 +1542,33 @@ void k_runs(RunArgs a) {
         if (p < n) run += s_v[pd(p)];
       }
     }
-    if (tid < 2) lb_store(a.lb + 2ull * t + tid, (t == 0 ? kLbInc : kLbAgg) | (tid == 0 ? TH : TV));
-    if (wv < 2) {  // wave 0: head channel, wave 1: value channel
-      const uint32_t ch = wv;
-      uint64_t excl = 0;
-      if (t > 0) {
-        excl = lb_walk_wave(a.lb, 2, ch, t);
-        if ((tid & (kWave - 1)) == 0) lb_store(a.lb + 2ull * t + ch, kLbInc | (excl + (ch ? TV : TH)));
+    if (packed) {  // values << 31 | heads, walked by one wave
+      constexpr uint64_t M31 = (1ull << 31) - 1;
+      const uint64_t mine = ((uint64_t)TV << 31) | TH;
+      if (tid == 0) lb_store(a.lb + t, (t == 0 ? kLbInc : kLbAgg) | mine);
+      if (wv == 0) {
+        uint64_t excl = 0;
+        if (t > 0) {
+          excl = lb_walk_wave(a.lb, 1, 0, t);
+          if (tid == 0) lb_store(a.lb + t, kLbInc | (excl + mine));
+        }
+        if (tid == 0) {
+          s_H0 = excl & M31;
+          s_V0 = excl >> 31;
+        }
       }
-      if ((tid & (kWave - 1)) == 0) {
-        if (ch == 0) s_H0 = excl; else s_V0 = excl;
+    } else {
+      if (tid < 2) lb_store(a.lb + 2ull * t + tid, (t == 0 ? kLbInc : kLbAgg) | (tid == 0 ? TH : TV));
+      if (wv < 2) {  // wave 0: head channel, wave 1: value channel
+        const uint32_t ch = wv;
+        uint64_t excl = 0;
+        if (t > 0) {
+          excl = lb_walk_wave(a.lb, 2, ch, t);
+          if ((tid & (kWave - 1)) == 0) lb_store(a.lb + 2ull * t + ch, kLbInc | (excl + (ch ? TV : TH)));
+        }
+        if ((tid & (kWave - 1)) == 0) {
+          if (ch == 0) s_H0 = excl; else s_V0 = excl;
+        }
       }
     }
     __syncthreads();

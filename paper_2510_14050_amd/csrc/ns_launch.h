@@ -168,6 +168,7 @@ struct RunArgs {
   uint32_t wide;             // 0 or 1 (see above)
   const uint64_t *gather;    // mode 1 with wide: the matrix counts
   uint64_t lim;              // entries of keys / items / gather; head arrays hold lim + 2
+  uint64_t vlim;             // bound on the sum of all values (packets); 0 = unknown
 };
 hipError_t launch_runs(const ScanShape &sh, int mode, const RunArgs &a, uint64_t max_tiles,
                        hipStream_t s);
