@@ -248,7 +248,8 @@ int resolve_tuning(const ns_tuning_t *t, Shapes *sh) {
 // ... ends in items_in).
 int enqueue_columns(Ws &ws, const Shapes &sh, uint64_t *items, uint64_t *tmp,
                     const uint64_t *link_off, uint32_t W, uint64_t max_items, uint64_t *stats,
-                    hipStream_t s, const uint64_t *gather = nullptr, uint64_t packets = 0) {
+                    hipStream_t s, const uint64_t *gather = nullptr, uint64_t packets = 0,
+                    bool hist_ready = false) {
   const Layout &L = ws.L;
   uint64_t *t_csort = ws.at<uint64_t>(L.t_csort), *t_run = ws.at<uint64_t>(L.t_run);
   uint32_t *chist = ws.at<uint32_t>(L.chist), *cbase = ws.at<uint32_t>(L.cbase);
@@ -261,7 +262,7 @@ int enqueue_columns(Ws &ws, const Shapes &sh, uint64_t *items, uint64_t *tmp,
   const uint64_t run_tiles = max_items / sh.scan.tile() + W + 1;
   {
     FillList f;
-    if (!chunked) f.add32(chist, (uint64_t)W * kColDigits * kBins);
+    if (!chunked && !hist_ready) f.add32(chist, (uint64_t)W * kColDigits * kBins);
     f.add64(lbs, run_tiles * 2);
     f.add64(col_off, (uint64_t)W + 1);
     f.add64(hpos, 1);
@@ -269,8 +270,10 @@ int enqueue_columns(Ws &ws, const Shapes &sh, uint64_t *items, uint64_t *tmp,
     HIP_TRY(launch_fill_multi(f, s));
   }
   if (!chunked) {
+    // (hist_ready: the run-length pass counted the items' digits as it wrote them)
     const uint64_t hist_tiles = max_items / kHistTile + W + 1;
-    HIP_TRY(timed(K_HIST, s, [&] { return launch_hist_items(items, link_off, t_chist, W, hist_tiles, chist, s); }));
+    if (!hist_ready)
+      HIP_TRY(timed(K_HIST, s, [&] { return launch_hist_items(items, link_off, t_chist, W, hist_tiles, chist, s); }));
     HIP_TRY(timed(K_HSCAN, s, [&] { return launch_hist_scan(chist, cbase, (uint64_t)W * kColDigits, s); }));
   }
   const uint64_t sort_tiles = max_items / sh.sort.tile() + W + 1;
@@ -420,9 +423,14 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
   // run-length encoding (+ rows and column items when statistics are wanted)
   uint64_t *lbs = ws.at<uint64_t>(L.lbs);
   uint64_t *items = nullptr, *rpos = nullptr, *rlink = nullptr;
+  // one large segment whose sorts are not chunked (the column sort takes the
+  // same path as the key sort): the run-length pass also counts the column
+  // items' digits
+  const bool col_hist = want_stats && !chunked && rle_one_large_segment(sh.scan, W, rle_tiles, N);
   {
     FillList f;
     f.add64(lbs, rle_tiles * 2);
+    if (col_hist) f.add32(ws.at<uint32_t>(L.chist), (uint64_t)kColDigits * kBins);
     if (want_stats) {
       items = ws.at<uint64_t>(L.KA) == sorted ? ws.at<uint64_t>(L.KB) : ws.at<uint64_t>(L.KA);
       rpos = ws.at<uint64_t>(L.HA);
@@ -452,13 +460,14 @@ int enqueue_packets(Ws &ws, const Shapes &sh, const uint32_t *src, const uint32_
   r.lb = lbs;
   r.ticket = ws.ticket();
   r.lim = N;
+  r.col_hist = col_hist ? ws.at<uint32_t>(L.chist) : nullptr;
   HIP_TRY(timed(K_RLE, s, [&] { return launch_rle(sh.scan, r, rle_tiles, s); }));
   if (!want_stats) return NS_OK;
   // rows: packets = distance between row heads, fan-out = links between them
   HIP_TRY(timed(K_SEGMAX, s, [&] { return launch_segmax(rpos, rlink, row_off, W, N, o.stats, 4, 5, s); }));
   // columns: items are sorted in place (ping-pong with the other sort buffer)
   uint64_t *tmp = (items == ws.at<uint64_t>(L.KA)) ? ws.at<uint64_t>(L.KB) : ws.at<uint64_t>(L.KA);
-  int rc = enqueue_columns(ws, sh, items, tmp, link_off, W, N, o.stats, s, nullptr, N);
+  int rc = enqueue_columns(ws, sh, items, tmp, link_off, W, N, o.stats, s, nullptr, N, col_hist);
   if (rc) return rc;
   HIP_TRY(timed(K_FINAL, s, [&] { return launch_finalize(seg_off, link_off, row_off, ws.at<uint64_t>(L.col_off), W, o.stats, s); }));
   return NS_OK;

@@ -1239,6 +1239,7 @@ void k_rle(RleArgs a) {
   __shared__ uint16_t s_hpos[TILE];   // link head positions in the tile
   __shared__ uint16_t s_rpos[ROWS_LDS ? TILE : 1];  // row head positions
   __shared__ uint16_t s_rlr[ROWS_LDS ? TILE : 1];   // tile-local link rank of each row head
+  __shared__ uint32_t s_ch[ROWS_LDS ? 1 : kColDigits * kBins];  // column digit counts
   __shared__ uint64_t s_tmp[BLOCK / kWave];
   __shared__ uint64_t s_L0, s_R0, s_trail, s_base;
   __shared__ uint32_t s_next, s_next_w;
@@ -1247,6 +1248,9 @@ void k_rle(RleArgs a) {
   const uint64_t total = ld_const(a.tile_off + a.W);
   const bool in_place = a.ukeys == a.keys;
   const bool packed = a.lim < (1ull << 31);  // one look-back word per tile
+  const bool col_hist = !ROWS_LDS && a.col_hist;
+  if (col_hist)
+    for (int i = tid; i < kColDigits * kBins; i += BLOCK) s_ch[i] = 0;
   if (wv == 3) claim_tile(a.ticket, a.tile_off, a.W, total, &s_next, &s_next_w);
   __syncthreads();
   ScanTile g = scan_tile(a.tile_off, a.seg_off, s_next, s_next_w, total, TILE);
@@ -1399,6 +1403,11 @@ void k_rle(RleArgs a) {
         a.win_counts[wpos + r] = cnt;
       }
       if (a.items) a.items[L] = (K << 32) | cnt;
+      if (col_hist) {  // the item's destination digits, for the column sort
+#pragma unroll
+        for (int q = 0; q < kColDigits; ++q)
+          atomicAdd(&s_ch[q * kBins + (((uint32_t)K >> (8 * q)) & 255)], 1u);
+      }
     }
     if (ROWS_LDS && a.rpos) {
       for (uint32_t q = tid; q < TR; q += BLOCK) {
@@ -1422,6 +1431,10 @@ void k_rle(RleArgs a) {
       }
     }
     __syncthreads();
+  }
+  if (col_hist) {  // after the loop's last barrier: this workgroup's counts
+    for (int i = tid; i < kColDigits * kBins; i += BLOCK)
+      if (s_ch[i]) atomicAdd(&a.col_hist[i], s_ch[i]);
   }
 }
 
@@ -2430,14 +2443,17 @@ static hipError_t rle_impl(const RleArgs &a, uint64_t max_tiles, hipStream_t s) 
   return hipGetLastError();
 }
 
+// one segment of 2^24 keys or more: 3 workgroups per CU, rows from registers
+// (2^30 keys: 4.77 vs 4.98 ms; 8192 windows of 2^17 keys lose, 7.5 vs 6.0 ms)
+bool rle_one_large_segment(const ScanShape &sh, uint32_t W, uint64_t max_tiles, uint64_t lim) {
+  return sh.items == 16 && W == 1 && max_tiles * 256 * 16 >= (1ull << 24) && lim < (1ull << 31);
+}
+
 hipError_t launch_rle(const ScanShape &sh, const RleArgs &a, uint64_t max_tiles, hipStream_t s) {
   if (sh.items == 4) return rle_impl<4>(a, max_tiles, s);
   if (sh.items == 8) return rle_impl<8>(a, max_tiles, s);
   if (sh.items == 16) {
-    // one segment of 2^24 keys or more: 3 workgroups per CU, rows from registers
-    // (2^30 keys: 4.77 vs 4.98 ms; 8192 windows of 2^17 keys lose, 7.5 vs 6.0 ms)
-    if (a.W == 1 && max_tiles * 256 * 16 >= (1ull << 24) && a.lim < (1ull << 31))
-      return rle_impl<16, false>(a, max_tiles, s);
+    if (rle_one_large_segment(sh, a.W, max_tiles, a.lim)) return rle_impl<16, false>(a, max_tiles, s);
     return rle_impl<16>(a, max_tiles, s);
   }
   return hipErrorInvalidValue;

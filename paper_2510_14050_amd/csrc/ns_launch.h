@@ -143,8 +143,13 @@ struct RleArgs {
   uint64_t *lb;        // [tiles][2]
   uint32_t *ticket;
   uint64_t lim;        // positions (and so links) of the input; head arrays hold lim + 2
+  uint32_t *col_hist;  // nullable, with rle_one_large_segment only: the column items'
+                       // destination-digit counts [4][256] are added here (zeroed by the caller)
 };
 hipError_t launch_rle(const ScanShape &sh, const RleArgs &a, uint64_t max_tiles, hipStream_t s);
+// whether launch_rle takes its single-large-segment variant (rows from
+// registers, one look-back word per tile, column histogram on the way)
+bool rle_one_large_segment(const ScanShape &sh, uint32_t W, uint64_t max_tiles, uint64_t lim);
 
 // --- run reduction over a sorted array with explicit values -----------------------
 // mode 0: rows of a matrix (group = key>>32, value = counts[p]); also emits
