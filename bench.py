@@ -184,7 +184,7 @@ class PlainPath:
             ns.stats(mats[0], self.st_a, self.ws)
 
 
-def bytes_model(N, W, got, got_agg, per_window, aggregate, cmin, bits):
+def bytes_model(N, W, got, got_agg, per_window, aggregate, cmin, bits, scan_items=8):
     """Bytes the design as built moves for one step, from the measured links,
     sources and destinations of each pipeline that runs:
       sort with look-back: 8 (histogram) + 8 x 16 (key passes)
@@ -193,22 +193,26 @@ def bytes_model(N, W, got, got_agg, per_window, aggregate, cmin, bits):
       run-length: 8 read + 24 per link (items + the per-window matrix, or the
         aggregate's keys and counts) + 16 per row head
       row maxima: 16 per row head
-      columns: 8 per link (histogram; look-back only) + 4 x 16 per link
-        (passes; chunked: 32 / bits passes of 8 + 16) + 8 per link (run
-        reduce) + 16 per column head, and 16 per column head for the maxima."""
+      columns: 8 per link (histogram; look-back only, and not for one segment
+        of 2^24 to 2^31 keys with run-length tiles of 16 keys per thread,
+        whose run-length pass counts the digits) + 4 x 16 per link (passes;
+        chunked: 32 / bits passes of 8 + 16) + 8 per link (run reduce) + 16
+        per column head, and 16 per column head for the maxima."""
     P, Pc = -(-64 // bits), -(-32 // bits)
 
-    def pipe(n, links, rows, cols, chunked):
+    def pipe(n, links, rows, cols, chunked, segments):
+        fused = (not chunked and segments == 1 and scan_items == 16
+                 and (1 << 24) <= n < (1 << 31))
         b = (P * 24 if chunked else 8 + 8 * 16) * n
         b += 8 * n + 24 * links + 16 * rows + 16 * rows
-        b += (Pc * 24 if chunked else 8 + 4 * 16) * links + 8 * links + 32 * cols
+        b += (Pc * 24 if chunked else (0 if fused else 8) + 4 * 16) * links + 8 * links + 32 * cols
         return b
     total = 0
     if per_window:
         total += pipe(N, int(got[:, 1].sum()), int(got[:, 2].sum()), int(got[:, 3].sum()),
-                      W == 1 and N >= cmin)
+                      W == 1 and N >= cmin, W)
     if aggregate:
-        total += pipe(N, int(got_agg[1]), int(got_agg[2]), int(got_agg[3]), N >= cmin)
+        total += pipe(N, int(got_agg[1]), int(got_agg[2]), int(got_agg[3]), N >= cmin, 1)
     return total
 
 
@@ -254,7 +258,8 @@ def profiled_traffic(workload: str, kernel: str):
     return None
 
 
-def path_rates(workload, N, W, got, got_agg, ms_step, per_window, aggregate, cmin, bits):
+def path_rates(workload, N, W, got, got_agg, ms_step, per_window, aggregate, cmin, bits,
+               scan_items=8):
     """Whole-step rates: measured memory traffic (rocprofv3 FETCH_SIZE +
     WRITE_SIZE of every library kernel of one step, scaled by a 1 GiB copy;
     null unless taken on these sources), the model bytes of the design as
@@ -263,7 +268,7 @@ def path_rates(workload, N, W, got, got_agg, ms_step, per_window, aggregate, cmi
     t = _traffic_file()
     measured = (t or {}).get("step_traffic_bytes", {}).get(workload)
     sec = ms_step * 1e-3
-    M = bytes_model(N, W, got, got_agg, per_window, aggregate, cmin, bits)
+    M = bytes_model(N, W, got, got_agg, per_window, aggregate, cmin, bits, scan_items)
     links = int(got_agg[1]) if aggregate else int(got[:, 1].sum())
     S = sort_model_bytes(N, links)
     F = 8 * N + 64 * (W if per_window else 1)
@@ -418,7 +423,7 @@ def run_workload(name, args, dev, primary):
         res["kernels_ms"] = {k: {"ms": round(v[0], 4), "launches": v[1]} for k, v in kt.items()}
         log("kernel breakdown (eager, ms):", json.dumps(res["kernels_ms"]))
         res["path"] = path_rates(name, N, W, got, got_agg, ms_step, per_window, aggregate, cmin,
-                                 bits)
+                                 bits, shape.scan_items if shape else 8)
 
     if primary and aggregate and not args.no_analysis:
         res["analysis"] = analysis_leg(ns, torch, np, agg, ws, N, got_agg, args, dev)
